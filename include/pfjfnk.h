@@ -1,0 +1,231 @@
+/*
+ * pfjfnk.h -- C ABI of the MI355X (gfx950) matrix-free JFNK hot path for the
+ * implicit phase-field method of Ghosh, Newman & Francois, "Tusas: a fully
+ * implicit parallel approach for coupled phase-field equations".
+ *
+ * Problem (paper Sec. 2): nodal Q1 finite elements on a structured box mesh
+ * [-L0,L0] x [-L1,L1] (x [-L2,L2]) with n[k] elements and n[k]+1 nodes per
+ * axis, two fields per node (phi, u), backward Euler in time.  The discrete
+ * residual F(U; U^n) is
+ *
+ *   F1_i = (a^2 (phi - phi^n)/dt, psi_i) + (J(grad phi), grad psi_i)
+ *          - (phi - phi^3 - lambda (1 - phi^2)^2 u, psi_i)
+ *   F2_i = ((u - u^n)/dt - (phi - phi^n)/(2 dt), psi_i) + (D grad u, grad psi_i)
+ *
+ * with the fourfold anisotropy a(g) = 1 - 3 eps4 + 4 eps4 sum g_k^4/(|g|^2 +
+ * delta2)^2 (Eq. gs), J(g) = d/dg (a^2 |g|^2 / 2) (the variational form of the
+ * anisotropic terms of Eq. pf2), the lambda coupling of Eq. lambda, the thermal
+ * equation of Eq. temp1 and 3 Gauss points per axis (Secs. 4.1, 4.2).
+ *
+ * Vector layout: every state, residual and direction vector is a DEVICE array
+ * of 2 * n_nodes doubles, interleaved node-major: V[2*node + 0] = phi part,
+ * V[2*node + 1] = u part, node = i + (n0+1) * (j + (n1+1) * k).  All such
+ * arrays are owned by the caller (e.g. torch tensors), must be contiguous and
+ * 16-byte aligned, and may not alias each other unless a function says so.
+ *
+ * Streams: every call enqueues its work on the caller's hipStream_t passed as
+ * void* (NULL = default stream).  Calls marked [async] return after enqueue;
+ * calls marked [sync] synchronise the stream because the host takes
+ * decisions on device results (norms, Krylov coefficients).
+ *
+ * Errors: every function returns PF_OK (0) or a negative PF_ERR_* code;
+ * pf_last_error() returns a thread-local description of the last failure.
+ * Invalid arguments are detected on the host before anything is launched.
+ *
+ * Thread safety: a pf_problem handle is not thread-safe; use one per thread.
+ */
+#ifndef PFJFNK_H
+#define PFJFNK_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_OK 0
+#define PF_ERR_INVALID_ARG (-1)   /* null pointer, bad size, unsupported option */
+#define PF_ERR_HIP (-2)           /* a HIP runtime call failed                   */
+#define PF_ERR_NONFINITE (-3)     /* a residual norm became NaN or Inf           */
+#define PF_ERR_NOT_CONVERGED (-4) /* Newton hit max_newton before Eq. tolerance  */
+#define PF_ERR_LINEAR (-5)        /* FGMRES did not reach its tolerance          */
+#define PF_ERR_LINESEARCH (-6)    /* no Lambda satisfied Eq. glob                */
+#define PF_ERR_OOM (-7)           /* device allocation failed                    */
+
+#define PF_JV_FD 0       /* (F(U + eps v) - F(U))/eps, Eq. JFmatvec           */
+#define PF_JV_ANALYTIC 1 /* exact tangent of the residual                     */
+
+#define PF_PC_NONE 0   /* M = I                                               */
+#define PF_PC_JACOBI 1 /* M = diag of the blocks of Eq. pre                   */
+#define PF_PC_GMG 2    /* one geometric V-cycle per block of Eq. pre          */
+
+#define PF_FP64 0
+#define PF_FP32 1
+
+#define PF_MAX_LOG 64
+
+/* Model and mesh.  dim = 2 or 3; n[k] >= 1 elements per axis (n[2] ignored
+ * in 2-D); half_width[k] > 0.  dt > 0, D > 0, delta2 > 0 (regularises the
+ * anisotropy where grad phi = 0; 1e-16 is the default reading). */
+typedef struct {
+  int dim;
+  int n[3];
+  double half_width[3];
+  double dt;
+  double eps4;
+  double lambda;
+  double D;
+  double delta2;
+} pf_params;
+
+/* Newton-Krylov options (Sec. 2.2).  The forcing term follows Eqs. force1 to
+ * forcing: eta_0 = eta0, eta_l = min(eta_max, max(gamma (|F_l|/|F_{l-1}|)^omega,
+ * gamma eta_{l-1}^omega, eta_min)).  gmres_m is the restart length (<= the
+ * value given to pf_create), gmres_maxit the total FGMRES iteration cap per
+ * linear solve. */
+typedef struct {
+  double tau_r;
+  double tau_a;
+  int max_newton;
+  int max_backtracks;
+  int gmres_m;
+  int gmres_maxit;
+  double eta0;
+  double eta_min;
+  double eta_max;
+  double gamma;
+  double omega;
+  int jv_mode;      /* PF_JV_FD or PF_JV_ANALYTIC */
+  int pc;           /* PF_PC_NONE, PF_PC_JACOBI or PF_PC_GMG */
+  int pc_precision; /* PF_FP64 or PF_FP32 (GMG only) */
+} pf_solver_opts;
+
+/* Statistics of one pf_newton_step / pf_linear_solve / pf_adjoint_step call.
+ * Times are host wall-clock milliseconds per phase (stream synchronised at
+ * phase ends only when the call is [sync] anyway). */
+typedef struct {
+  int status;
+  int newton_its;
+  int gmres_its_total;
+  int backtracks;
+  double f0;
+  double f_final;
+  int gmres_its[PF_MAX_LOG];
+  double fnorm[PF_MAX_LOG + 1];
+  double t_total_ms;
+} pf_solver_stats;
+
+typedef struct pf_problem pf_problem;
+
+/* Fill opts with the paper's nonlinear-solver values (Sec. 4.1: eta0 = 0.1,
+ * eta_min = 1e-6, eta_max = 0.01, omega = 1.5, gamma = 0.9, tau_a = 0) with
+ * tau_r = 1e-10, FGMRES(30), at most 300 iterations per solve, 8 backtracks,
+ * 30 Newton iterations, FD Jv, FP64 GMG.  Host only. */
+void pf_default_opts(pf_solver_opts* opts);
+
+/* Create a problem: validates params, allocates every device workspace the
+ * other calls need (FGMRES basis for restart length gmres_m_max, multigrid
+ * hierarchy, reduction buffers) on the current HIP device.  *out receives the
+ * handle.  Returns PF_ERR_INVALID_ARG or PF_ERR_OOM on failure. */
+int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out);
+
+/* Free the handle and its workspaces (synchronises the device). */
+int pf_destroy(pf_problem* pb);
+
+/* Replace the scalar model parameters (dt, eps4, lambda, D, delta2) of an
+ * existing handle; mesh fields of params must match the handle.  Host only. */
+int pf_set_params(pf_problem* pb, const pf_params* params);
+
+/* Number of nodes and of unknowns (2 * nodes) of the handle's mesh. */
+long long pf_num_nodes(const pf_problem* pb);
+
+/* [async] F = F(U; Uprev), the residual above (Sec. 2.1.2, Eqs. dpf, dtemp
+ * with theta = 1).  U, Uprev, F: device, 2*n_nodes doubles.  F must not alias
+ * U or Uprev. */
+int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F, void* stream);
+
+/* [async] Jacobian-vector product Jv = F'(U) v (Sec. 2.2).
+ * mode PF_JV_FD: Jv = (F(U + eps v) - F0)/eps (Eq. JFmatvec) with
+ *   eps = sqrt(2^-52) (1 + |U|_2)/|v|_2 computed on the device; F0 must be
+ *   F(U; Uprev) (computed internally when F0 is NULL).
+ * mode PF_JV_ANALYTIC: the exact tangent of the residual; F0 is ignored.
+ * v == 0 gives Jv = 0.  Jv must not alias the inputs. */
+int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v,
+           const double* F0, int mode, double* Jv, void* stream);
+
+/* [async] Vector-Jacobian product for the cotangent w:
+ *   gU     = (dF/dU)^T w         (may be NULL)
+ *   gUprev = (dF/dUprev)^T w     (may be NULL)
+ *   gparams[0] = w . dF/d eps4, gparams[1] = w . dF/d lambda  (device, 2
+ *   doubles; may be NULL).  Reductions are deterministic. */
+int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w,
+           double* gU, double* gUprev, double* gparams, void* stream);
+
+/* [async] Build the preconditioner of Eq. pre at the state U: the blocks
+ * M11 = (1/dt)(c psi_j, psi_i) + (c grad psi_j, grad psi_i) with c the cell
+ * mean of a(grad phi)^2 (Eqs. m11, pref2 with k = 1) and
+ * M22 = (1/dt)(psi_j, psi_i) + D (grad psi_j, grad psi_i) (Eqs. m22,
+ * preconc2).  kind: PF_PC_NONE, PF_PC_JACOBI, PF_PC_GMG; precision PF_FP64 or
+ * PF_FP32 (the GMG V-cycle's arithmetic; Jacobi is always FP64). */
+int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, void* stream);
+
+/* [async] z = M^-1 r with the preconditioner of the last pf_precond_setup
+ * (Jacobi: diagonal scaling; GMG: one V-cycle per block).  M^-1 is linear and
+ * symmetric.  z must not alias r. */
+int pf_precond_apply(pf_problem* pb, const double* r, double* z, void* stream);
+
+/* [sync] Solve F'(U) x = b (transpose = 0) or F'(U)^T x = b (transpose = 1)
+ * by right-preconditioned FGMRES with the preconditioner already set up, to
+ * |b - A x| <= rtol |b| starting from x = 0.  The transposed solve uses the
+ * VJP as its operator (opts->jv_mode is then ignored).  Returns PF_ERR_LINEAR
+ * when opts->gmres_maxit iterations do not reach rtol (x holds the last
+ * iterate). */
+int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const double* b,
+                    double* x, int transpose, double rtol, const pf_solver_opts* opts,
+                    pf_solver_stats* stats, void* stream);
+
+/* [sync] One backward-Euler step: Newton-Krylov (Sec. 2.2) for
+ * F(U; Uprev) = 0 starting from U_inout, with the forcing term, the
+ * backtracking of Eq. glob (Lambda halved up to max_backtracks times), the
+ * termination test of Eq. tolerance and the preconditioner rebuilt at every
+ * Newton iterate.  On success U_inout holds the solution.  On failure it holds
+ * the last accepted iterate and the code says why. */
+int pf_newton_step(pf_problem* pb, const double* Uprev, double* U_inout,
+                   const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
+
+/* [sync] steps backward-Euler steps from states[0]: states is a device array
+ * of (steps + 1) * 2 * n_nodes doubles holding U^0 on entry; on return
+ * states[k] = U^k (the checkpoints of the adjoint).  Each step starts Newton
+ * from the previous state.  stats (optional) receives the last step's
+ * statistics with gmres_its_total and newton_its summed over steps. */
+int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
+              pf_solver_stats* stats, void* stream);
+
+/* [sync] One step of the discrete adjoint of backward-Euler stepping, for the
+ * step U = U^k from Uprev = U^{k-1}:  solve F'(U)^T lam = mu by FGMRES with
+ * the preconditioner rebuilt at U, then
+ *   mu_prev = -(dF/dUprev)^T lam       (device, 2*n_nodes; may be NULL)
+ *   gparams[0..1] -= (lam . dF/d eps4, lam . dF/d lambda)   (device, 2 doubles)
+ * lam (device, 2*n_nodes) receives the multiplier.  rtol = opts->tau_r. */
+int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const double* mu,
+                    double* lam, double* mu_prev, double* gparams, const pf_solver_opts* opts,
+                    pf_solver_stats* stats, void* stream);
+
+/* [async] Misfit of the phase field against a target:
+ *   L = 1/2 sum_i m_i (phi_i - phi*_i)^2 with the lumped nodal mass
+ *   m_i = integral of psi_i;  *L_dev (device double) receives L and dLdU
+ *   (device, 2*n_nodes) the gradient (zero u part).  phi_target: device,
+ *   n_nodes doubles. */
+int pf_misfit(pf_problem* pb, const double* U, const double* phi_target, double* L_dev,
+              double* dLdU, void* stream);
+
+/* [async] Deterministic dot product *out_dev = x . y over 2*n_nodes entries
+ * (device result).  Exposed for tests of the reduction kernels. */
+int pf_dot(pf_problem* pb, const double* x, const double* y, double* out_dev, void* stream);
+
+/* Thread-local message describing the last error ("" if none). */
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFJFNK_H */

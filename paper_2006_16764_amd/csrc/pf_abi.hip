@@ -1,0 +1,783 @@
+// C ABI of libpfjfnk: handle management, the residual-family entry points,
+// and the host drivers of the Newton-Krylov method (Sec. 2.2 of the paper):
+// right-preconditioned flexible GMRES with classical Gram-Schmidt applied twice
+// (FP64 Arnoldi, one host synchronisation per iteration), inexact Newton with
+// the forcing term of Eqs. force1-forcing, the backtracking of Eq. glob and
+// the termination test of Eq. tolerance; backward-Euler stepping and one step
+// of its discrete adjoint.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pf_internal.h"
+
+namespace pf {
+
+int elem_blocks(const pf_problem* pb);
+constexpr int kNumTmp = 6;
+static_assert(sizeof(((pf_problem*)nullptr)->tmp_vec) == kNumTmp * sizeof(double*), "tmp_vec size");
+
+namespace {
+thread_local std::string g_last_error;
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+__global__ void k_misfit(Geo G, const double2* __restrict__ U, const double* __restrict__ target,
+                         double2* __restrict__ g, double* __restrict__ partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < G.n_nodes;
+       i += (long long)gridDim.x * 256) {
+    const long long nn0 = G.nn[0], nn1 = G.nn[1];
+    const int ix = (int)(i % nn0);
+    const long long r = i / nn0;
+    const int iy = G.dim == 2 ? (int)r : (int)(r % nn1);
+    const int iz = G.dim == 2 ? 0 : (int)(r / nn1);
+    // lumped mass: integral of psi_i = prod_k h_k (halved on boundary planes)
+    double m = G.h[0] * ((ix == 0 || ix == G.n[0]) ? 0.5 : 1.0);
+    m *= G.h[1] * ((iy == 0 || iy == G.n[1]) ? 0.5 : 1.0);
+    if (G.dim == 3) m *= G.h[2] * ((iz == 0 || iz == G.n[2]) ? 0.5 : 1.0);
+    const double d = U[i].x - target[i];
+    if (g) g[i] = make_double2(m * d, 0.0);
+    acc = fma(0.5 * m * d, d, acc);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+int check_vec(const void* p, const char* name) {
+  if (!p) {
+    set_error(std::string("null device pointer: ") + name);
+    return PF_ERR_INVALID_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(p) % 16 != 0) {
+    set_error(std::string("device array not 16-byte aligned: ") + name);
+    return PF_ERR_INVALID_ARG;
+  }
+  return PF_OK;
+}
+
+int check_params(const pf_params* p) {
+  if (!p) {
+    set_error("params is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (p->dim != 2 && p->dim != 3) {
+    set_error("dim must be 2 or 3");
+    return PF_ERR_INVALID_ARG;
+  }
+  long long nodes = 1;
+  for (int k = 0; k < p->dim; ++k) {
+    if (p->n[k] < 1 || p->n[k] > (1 << 20) || !(p->half_width[k] > 0.0)) {
+      set_error("each n[k] must be in [1, 2^20] and half_width[k] > 0");
+      return PF_ERR_INVALID_ARG;
+    }
+    nodes *= (p->n[k] + 1);
+  }
+  if (nodes > (1LL << 31)) {
+    set_error("mesh too large (more than 2^31 nodes)");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!(p->dt > 0.0) || !(p->D > 0.0) || !(p->delta2 > 0.0) || !std::isfinite(p->eps4) ||
+      !std::isfinite(p->lambda)) {
+    set_error("dt, D, delta2 must be > 0 and eps4, lambda finite");
+    return PF_ERR_INVALID_ARG;
+  }
+  return PF_OK;
+}
+
+int check_opts(const pf_problem* pb, const pf_solver_opts* o) {
+  if (!o) {
+    set_error("opts is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (o->gmres_m < 1 || o->gmres_m > pb->gmres_m_max || o->gmres_maxit < 1 || o->max_newton < 0 ||
+      o->max_backtracks < 0 || (o->jv_mode != PF_JV_FD && o->jv_mode != PF_JV_ANALYTIC) ||
+      o->pc < PF_PC_NONE || o->pc > PF_PC_GMG ||
+      (o->pc_precision != PF_FP64 && o->pc_precision != PF_FP32) || !(o->tau_r >= 0.0) ||
+      !(o->tau_a >= 0.0)) {
+    set_error("invalid solver options (gmres_m must be in [1, gmres_m_max])");
+    return PF_ERR_INVALID_ARG;
+  }
+  return PF_OK;
+}
+
+// Copy n doubles from device to the pinned staging buffer and wait.
+int fetch(pf_problem* pb, const double* dev, int n, hipStream_t s) {
+  PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  PF_HIP_CHECK(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+int norm2(pf_problem* pb, const double* x, double* out, hipStream_t s) {
+  PF_TRY(blas_multidot(pb, x, pb->n_dof, 1, x, pb->n_dof, pb->red_out + 250, s));
+  PF_TRY(fetch(pb, pb->red_out + 250, 1, s));
+  *out = std::sqrt(pb->host_pinned[0]);
+  return PF_OK;
+}
+
+// Linear operator of a Krylov solve.
+struct Op {
+  pf_problem* pb;
+  const double* U;
+  const double* Uprev;
+  const double* F0;  // F(U) for the FD product
+  int kind;          // 0 = J (FD), 1 = J (analytic), 2 = J^T
+  int apply(const double* z, double* w, hipStream_t s) const {
+    if (kind == 0) {
+      PF_TRY(blas_fd_eps(pb, U, z, pb->n_dof, pb->eps_dev, s));
+      return launch_residual_family(pb, MODE_FD, U, Uprev, z, F0, pb->eps_dev, w, nullptr, nullptr, s);
+    }
+    if (kind == 1)
+      return launch_residual_family(pb, MODE_JVP, U, Uprev, z, nullptr, nullptr, w, nullptr, nullptr, s);
+    return launch_residual_family(pb, MODE_VJP, U, Uprev, z, nullptr, nullptr, w, nullptr,
+                                  pb->vjp_partials, s);
+  }
+};
+
+// Right-preconditioned FGMRES(m) from x = 0 for A x = b, |b - A x| <= rtol |b|.
+int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol,
+           const pf_solver_opts& o, int* its_out, hipStream_t s) {
+  const long long n = pb->n_dof;
+  const int m = o.gmres_m;
+  double* V = pb->V;
+  double* Z = pb->Z;
+  double* r = pb->tmp_vec[3];
+  double* h1 = pb->red_out;
+  double* h2 = pb->red_out + 64;
+  double* nw = pb->red_out + 128;
+  double* ydev = pb->red_out + 300;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  PF_HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  double beta;
+  PF_TRY(norm2(pb, b, &beta, s));
+  *its_out = 0;
+  if (!std::isfinite(beta)) {
+    set_error("non-finite right-hand side in FGMRES");
+    return PF_ERR_NONFINITE;
+  }
+  if (beta == 0.0) return PF_OK;
+  const double target = rtol * beta;
+  const double* rhs = b;
+  int total = 0;
+  bool converged = false;
+  double resid = beta;
+  while (true) {
+    // V_0 = r / beta
+    PF_TRY(blas_axpby(1.0 / resid, rhs, 0.0, rhs, V, n, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = resid;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (long long)j * n;
+      double* zj = Z + (long long)j * n;
+      double* w = V + (long long)(j + 1) * n;
+      PF_TRY(pc_apply(pb, vj, zj, s));
+      PF_TRY(op.apply(zj, w, s));
+      // classical Gram-Schmidt, twice
+      PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h1, s));
+      PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nullptr, 0, s));
+      PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h2, s));
+      PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
+      PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, h1, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PF_HIP_CHECK(hipStreamSynchronize(s));
+      const double* hp = pb->host_pinned;
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hp[i] + hp[64 + i];
+      const double hn = std::sqrt(hp[128]);
+      H[(j + 1) * m + j] = hn;
+      if (!std::isfinite(hn)) {
+        set_error("non-finite Arnoldi coefficient in FGMRES");
+        return PF_ERR_NONFINITE;
+      }
+      if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[j * m + j], c = H[(j + 1) * m + j];
+      const double rr = std::hypot(a, c);
+      cs[j] = rr > 0.0 ? a / rr : 1.0;
+      sn[j] = rr > 0.0 ? c / rr : 0.0;
+      H[j * m + j] = rr;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      jend = j + 1;
+      resid = std::fabs(g[j + 1]);
+      if (resid <= target) {
+        converged = true;
+        break;
+      }
+      if (total >= o.gmres_maxit || hn == 0.0) break;
+    }
+    // y = H^-1 g (upper triangular), x += Z y
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < jend; ++k) t -= H[i * m + k] * y[k];
+      y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
+    }
+    std::memcpy(pb->host_pinned + 160, y.data(), jend * sizeof(double));
+    PF_HIP_CHECK(hipMemcpyAsync(ydev, pb->host_pinned + 160, jend * sizeof(double),
+                                hipMemcpyHostToDevice, s));
+    PF_TRY(blas_combine(pb, Z, n, jend, ydev, x, n, s));
+    PF_HIP_CHECK(hipStreamSynchronize(s));
+    if (converged || total >= o.gmres_maxit) break;
+    // restart: r = b - A x
+    PF_TRY(op.apply(x, r, s));
+    PF_TRY(blas_axpby(1.0, b, -1.0, r, r, n, s));
+    PF_TRY(norm2(pb, r, &resid, s));
+    if (resid <= target) {
+      converged = true;
+      break;
+    }
+    rhs = r;
+  }
+  *its_out = total;
+  if (!converged) {
+    set_error("FGMRES did not reach its tolerance");
+    return PF_ERR_LINEAR;
+  }
+  return PF_OK;
+}
+
+void stats_reset(pf_solver_stats* st) {
+  if (st) std::memset(st, 0, sizeof(*st));
+}
+
+int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_opts& o,
+                pf_solver_stats* st, hipStream_t s) {
+  const long long n = pb->n_dof;
+  double* F = pb->tmp_vec[0];
+  double* dU = pb->tmp_vec[1];
+  double* Ut = pb->tmp_vec[2];
+  double* rhs = pb->tmp_vec[3] + 0;  // reused as FGMRES restart vector only after rhs is consumed
+  double* Ft = pb->tmp_vec[4];
+  double* B = pb->tmp_vec[5];
+  (void)rhs;
+  PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, nullptr, s));
+  double f;
+  PF_TRY(norm2(pb, F, &f, s));
+  if (!std::isfinite(f)) {
+    set_error("non-finite initial residual norm");
+    if (st) st->status = PF_ERR_NONFINITE;
+    return PF_ERR_NONFINITE;
+  }
+  const double f0 = f;
+  if (st) {
+    st->f0 = f0;
+    st->fnorm[0] = f0;
+  }
+  double eta = o.eta0;
+  int l = 0;
+  while (!(f < o.tau_r * f0 + o.tau_a)) {
+    if (l >= o.max_newton) {
+      set_error("Newton did not converge within max_newton iterations");
+      if (st) {
+        st->status = PF_ERR_NOT_CONVERGED;
+        st->f_final = f;
+      }
+      return PF_ERR_NOT_CONVERGED;
+    }
+    PF_TRY(pc_setup(pb, U, o.pc, o.pc_precision, s));
+    PF_TRY(blas_axpby(-1.0, F, 0.0, F, B, n, s));
+    Op op{pb, U, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
+    int its = 0;
+    int rc = fgmres(pb, op, B, dU, eta, o, &its, s);
+    if (st) {
+      st->gmres_its_total += its;
+      if (l < PF_MAX_LOG) st->gmres_its[l] = its;
+    }
+    if (rc != PF_OK && rc != PF_ERR_LINEAR) {
+      if (st) st->status = rc;
+      return rc;
+    }
+    // backtracking: Lambda = 1, 1/2, ... until |F(U + Lambda dU)| <= |F(U)|
+    double lam = 1.0, ft = 0.0;
+    bool ok = false;
+    for (int bt = 0; bt <= o.max_backtracks; ++bt) {
+      PF_TRY(blas_axpby(1.0, U, lam, dU, Ut, n, s));
+      PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr, nullptr, s));
+      PF_TRY(norm2(pb, Ft, &ft, s));
+      if (std::isfinite(ft) && ft <= f) {
+        ok = true;
+        break;
+      }
+      lam *= 0.5;
+      if (st) st->backtracks++;
+    }
+    if (!ok) {
+      set_error("line search failed to reduce |F|");
+      if (st) {
+        st->status = std::isfinite(ft) ? PF_ERR_LINESEARCH : PF_ERR_NONFINITE;
+        st->f_final = f;
+      }
+      return std::isfinite(ft) ? PF_ERR_LINESEARCH : PF_ERR_NONFINITE;
+    }
+    PF_HIP_CHECK(hipMemcpyAsync(U, Ut, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PF_HIP_CHECK(hipMemcpyAsync(F, Ft, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // forcing term for the next linear solve
+    const double ratio = ft / f;
+    double en = o.gamma * std::pow(ratio, o.omega);
+    const double safeg = o.gamma * std::pow(eta, o.omega);
+    en = std::max(en, safeg);
+    en = std::max(en, o.eta_min);
+    eta = std::min(o.eta_max, en);
+    f = ft;
+    ++l;
+    if (st && l <= PF_MAX_LOG) st->fnorm[l] = f;
+  }
+  if (st) {
+    st->newton_its = l;
+    st->f_final = f;
+    st->status = PF_OK;
+  }
+  return PF_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// HIP keeps one sticky "last error" per thread that any runtime call (ours or
+// another library's) may set.  Entry points clear it first so that the checks
+// after their own launches report only their own failures.
+void clear_stale_error() { (void)hipGetLastError(); }
+
+Geo make_geo(const pf_params& p) {
+  Geo G{};
+  G.dim = p.dim;
+  G.n_nodes = 1;
+  G.n_elems = 1;
+  G.jac = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    if (k < p.dim) {
+      G.n[k] = p.n[k];
+      G.nn[k] = p.n[k] + 1;
+      G.h[k] = 2.0 * p.half_width[k] / p.n[k];
+      G.ih[k] = 1.0 / G.h[k];
+      G.jac *= 0.5 * G.h[k];
+    } else {
+      G.n[k] = 1;
+      G.nn[k] = 1;
+      G.h[k] = 1.0;
+      G.ih[k] = 1.0;
+    }
+    G.n_nodes *= G.nn[k];
+    G.n_elems *= (k < p.dim) ? G.n[k] : 1;
+  }
+  G.dt = p.dt;
+  G.idt = 1.0 / p.dt;
+  G.eps4 = p.eps4;
+  G.lam = p.lambda;
+  G.D = p.D;
+  G.delta2 = p.delta2;
+  return G;
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+extern "C" {
+
+void pf_default_opts(pf_solver_opts* o) {
+  if (!o) return;
+  o->tau_r = 1e-10;
+  o->tau_a = 0.0;
+  o->max_newton = 30;
+  o->max_backtracks = 8;
+  o->gmres_m = 30;
+  o->gmres_maxit = 300;
+  o->eta0 = 0.1;
+  o->eta_min = 1e-6;
+  o->eta_max = 0.01;
+  o->gamma = 0.9;
+  o->omega = 1.5;
+  o->jv_mode = PF_JV_FD;
+  o->pc = PF_PC_GMG;
+  o->pc_precision = PF_FP64;
+}
+
+const char* pf_last_error(void) { return g_last_error.c_str(); }
+
+int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
+  g_last_error.clear();
+  if (!out) {
+    set_error("out is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  PF_TRY(check_params(params));
+  if (gmres_m_max < 1 || gmres_m_max > 60) {
+    set_error("gmres_m_max must be in [1, 60]");
+    return PF_ERR_INVALID_ARG;
+  }
+  pf_problem* pb = new pf_problem();
+  std::memset(pb, 0, sizeof(*pb));
+  pb->params = *params;
+  pb->geo = make_geo(*params);
+  pb->n_dof = 2 * pb->geo.n_nodes;
+  pb->gmres_m_max = gmres_m_max;
+  PF_HIP_CHECK(hipGetDevice(&pb->device));
+  auto fail = [&](int rc) {
+    pf_destroy(pb);
+    return rc;
+  };
+  const long long n = pb->n_dof;
+  long long rb = (n / 2 + 255) / 256;
+  pb->n_red_blocks = (int)std::min<long long>(std::max<long long>(rb, 1), 1024);
+  pb->n_elem_blocks = elem_blocks(pb);
+  const int NA = 1 << pb->geo.dim;
+  pb->elem_buf_len = (long long)4 * NA * pb->geo.n_elems;
+  if (hipMalloc(&pb->red_partials, (size_t)64 * pb->n_red_blocks * sizeof(double)) != hipSuccess ||
+      hipMalloc(&pb->red_out, 512 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&pb->host_pinned, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&pb->elem_buf, (size_t)pb->elem_buf_len * sizeof(double)) != hipSuccess ||
+      hipMalloc(&pb->vjp_partials, (size_t)2 * pb->n_elem_blocks * sizeof(double)) != hipSuccess ||
+      hipMalloc(&pb->eps_dev, 8 * sizeof(double)) != hipSuccess) {
+    set_error("device allocation failed (workspace)");
+    return fail(PF_ERR_OOM);
+  }
+  for (int i = 0; i < kNumTmp; ++i) {
+    if (hipMalloc(&pb->tmp_vec[i], (size_t)n * sizeof(double)) != hipSuccess) {
+      set_error("device allocation failed (work vectors)");
+      return fail(PF_ERR_OOM);
+    }
+  }
+  if (hipMalloc(&pb->V, (size_t)(gmres_m_max + 1) * n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&pb->Z, (size_t)gmres_m_max * n * sizeof(double)) != hipSuccess) {
+    set_error("device allocation failed (Krylov basis)");
+    return fail(PF_ERR_OOM);
+  }
+  int rc = pc_alloc(pb);
+  if (rc != PF_OK) {
+    set_error("device allocation failed (preconditioner)");
+    return fail(rc);
+  }
+  *out = pb;
+  return PF_OK;
+}
+
+int pf_destroy(pf_problem* pb) {
+  if (!pb) return PF_OK;
+  int rc = PF_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && rc == PF_OK) {
+      set_error(std::string("pf_destroy: ") + what + ": " + hipGetErrorString(e));
+      rc = PF_ERR_HIP;
+    }
+  };
+  chk(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  chk(pc_free(pb), "preconditioner buffers");
+  double* bufs[] = {pb->red_partials, pb->red_out, pb->elem_buf, pb->vjp_partials, pb->eps_dev,
+                    pb->V, pb->Z};
+  const char* names[] = {"red_partials", "red_out", "elem_buf", "vjp_partials", "eps_dev", "V", "Z"};
+  for (int i = 0; i < 7; ++i)
+    if (bufs[i]) chk(hipFree(bufs[i]), names[i]);
+  for (int i = 0; i < kNumTmp; ++i)
+    if (pb->tmp_vec[i]) chk(hipFree(pb->tmp_vec[i]), "tmp_vec");
+  if (pb->host_pinned) chk(hipHostFree(pb->host_pinned), "host_pinned");
+  delete pb;
+  (void)hipGetLastError();  // leave no sticky error behind for other libraries
+  return rc;
+}
+
+int pf_set_params(pf_problem* pb, const pf_params* p) {
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_params(p));
+  if (p->dim != pb->params.dim) {
+    set_error("mesh of pf_set_params differs from the handle");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < p->dim; ++k) {
+    if (p->n[k] != pb->params.n[k] || p->half_width[k] != pb->params.half_width[k]) {
+      set_error("mesh of pf_set_params differs from the handle");
+      return PF_ERR_INVALID_ARG;
+    }
+  }
+  pb->params = *p;
+  pb->geo = make_geo(*p);
+  return PF_OK;
+}
+
+long long pf_num_nodes(const pf_problem* pb) { return pb ? pb->geo.n_nodes : -1; }
+
+int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(F, "F"));
+  return launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
+                                nullptr, S(stream));
+}
+
+int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v, const double* F0,
+           int mode, double* Jv, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(v, "v"));
+  PF_TRY(check_vec(Jv, "Jv"));
+  hipStream_t s = S(stream);
+  if (mode == PF_JV_ANALYTIC)
+    return launch_residual_family(pb, MODE_JVP, U, Uprev, v, nullptr, nullptr, Jv, nullptr, nullptr, s);
+  if (mode != PF_JV_FD) {
+    set_error("mode must be PF_JV_FD or PF_JV_ANALYTIC");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!F0) {
+    F0 = pb->tmp_vec[0];
+    PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr,
+                                  pb->tmp_vec[0], nullptr, nullptr, s));
+  } else {
+    PF_TRY(check_vec(F0, "F0"));
+  }
+  PF_TRY(blas_fd_eps(pb, U, v, pb->n_dof, pb->eps_dev, s));
+  return launch_residual_family(pb, MODE_FD, U, Uprev, v, F0, pb->eps_dev, Jv, nullptr, nullptr, s);
+}
+
+int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w, double* gU,
+           double* gUprev, double* gparams, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(w, "w"));
+  if (gU) PF_TRY(check_vec(gU, "gU"));
+  if (gUprev) PF_TRY(check_vec(gUprev, "gUprev"));
+  hipStream_t s = S(stream);
+  PF_TRY(launch_residual_family(pb, MODE_VJP, U, Uprev, w, nullptr, nullptr, gU, gUprev,
+                                pb->vjp_partials, s));
+  if (gparams) PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gparams, 1.0, s));
+  return PF_OK;
+}
+
+int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(U, "U"));
+  if (kind < PF_PC_NONE || kind > PF_PC_GMG || (precision != PF_FP64 && precision != PF_FP32)) {
+    set_error("invalid preconditioner kind or precision");
+    return PF_ERR_INVALID_ARG;
+  }
+  return pc_setup(pb, U, kind, precision, S(stream));
+}
+
+int pf_precond_apply(pf_problem* pb, const double* r, double* z, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(r, "r"));
+  PF_TRY(check_vec(z, "z"));
+  return pc_apply(pb, r, z, S(stream));
+}
+
+int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const double* b, double* x,
+                    int transpose, double rtol, const pf_solver_opts* opts, pf_solver_stats* stats,
+                    void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(b, "b"));
+  PF_TRY(check_vec(x, "x"));
+  hipStream_t s = S(stream);
+  stats_reset(stats);
+  const double t0 = now_ms();
+  double* F = pb->tmp_vec[0];
+  int kind = transpose ? 2 : (opts->jv_mode == PF_JV_FD ? 0 : 1);
+  if (kind == 0)
+    PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, nullptr, s));
+  Op op{pb, U, Uprev, F, kind};
+  int its = 0;
+  int rc = fgmres(pb, op, b, x, rtol, *opts, &its, s);
+  if (stats) {
+    stats->gmres_its_total = its;
+    stats->gmres_its[0] = its;
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int pf_newton_step(pf_problem* pb, const double* Uprev, double* U, const pf_solver_opts* opts,
+                   pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(U, "U"));
+  stats_reset(stats);
+  const double t0 = now_ms();
+  int rc = newton_impl(pb, Uprev, U, *opts, stats, S(stream));
+  if (stats) {
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
+              pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(states, "states"));
+  if (steps < 0) {
+    set_error("steps must be >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  const long long n = pb->n_dof;
+  pf_solver_stats acc;
+  stats_reset(&acc);
+  const double t0 = now_ms();
+  for (int k = 0; k < steps; ++k) {
+    double* prev = states + (long long)k * n;
+    double* next = prev + n;
+    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    pf_solver_stats st;
+    stats_reset(&st);
+    int rc = newton_impl(pb, prev, next, *opts, &st, s);
+    acc.newton_its += st.newton_its;
+    acc.gmres_its_total += st.gmres_its_total;
+    acc.backtracks += st.backtracks;
+    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
+    acc.f0 = st.f0;
+    acc.f_final = st.f_final;
+    if (rc != PF_OK) {
+      acc.status = rc;
+      if (stats) *stats = acc;
+      return rc;
+    }
+  }
+  acc.t_total_ms = now_ms() - t0;
+  if (stats) *stats = acc;
+  return PF_OK;
+}
+
+int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const double* mu,
+                    double* lam, double* mu_prev, double* gparams, const pf_solver_opts* opts,
+                    pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(mu, "mu"));
+  PF_TRY(check_vec(lam, "lam"));
+  if (mu_prev) PF_TRY(check_vec(mu_prev, "mu_prev"));
+  if (!gparams) {
+    set_error("gparams is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  stats_reset(stats);
+  const double t0 = now_ms();
+  PF_TRY(pc_setup(pb, U, opts->pc, opts->pc_precision, s));
+  Op op{pb, U, Uprev, nullptr, 2};
+  int its = 0;
+  int rc = fgmres(pb, op, mu, lam, opts->tau_r, *opts, &its, s);
+  if (stats) {
+    stats->gmres_its_total = its;
+    stats->gmres_its[0] = its;
+    stats->status = rc;
+  }
+  if (rc != PF_OK) return rc;
+  double* gP = pb->tmp_vec[4];
+  double* gp_local = pb->red_out + 400;
+  PF_TRY(launch_residual_family(pb, MODE_VJP, U, Uprev, lam, nullptr, nullptr, nullptr, gP,
+                                pb->vjp_partials, s));
+  PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gp_local, 1.0, s));
+  PF_TRY(blas_sub_scalars(gparams, gp_local, 2, s));
+  if (mu_prev) PF_TRY(blas_axpby(-1.0, gP, 0.0, gP, mu_prev, pb->n_dof, s));
+  PF_HIP_CHECK(hipStreamSynchronize(s));
+  if (stats) stats->t_total_ms = now_ms() - t0;
+  return PF_OK;
+}
+
+int pf_misfit(pf_problem* pb, const double* U, const double* phi_target, double* L_dev,
+              double* dLdU, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(U, "U"));
+  if (!phi_target || !L_dev) {
+    set_error("phi_target and L_dev must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (dLdU) PF_TRY(check_vec(dLdU, "dLdU"));
+  hipStream_t s = S(stream);
+  const int nb = pb->n_red_blocks;
+  hipLaunchKernelGGL(k_misfit, dim3(nb), dim3(256), 0, s, pb->geo,
+                     reinterpret_cast<const double2*>(U), phi_target,
+                     reinterpret_cast<double2*>(dLdU), pb->red_partials);
+  PF_HIP_CHECK(hipGetLastError());
+  return blas_reduce_partials(pb->red_partials, nb, 1, L_dev, 1.0, s);
+}
+
+int pf_dot(pf_problem* pb, const double* x, const double* y, double* out_dev, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(x, "x"));
+  PF_TRY(check_vec(y, "y"));
+  if (!out_dev) {
+    set_error("out_dev is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  return blas_dot(pb, x, y, pb->n_dof, out_dev, S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal definitions shared by the HIP translation units of libpfjfnk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pfjfnk.h"
+
+namespace pf {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_stale_error();
+
+#define PF_HIP_CHECK(call)                                                         \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::pf::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return PF_ERR_HIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+#define PF_TRY(call)              \
+  do {                            \
+    int rc_ = (call);             \
+    if (rc_ != PF_OK) return rc_; \
+  } while (0)
+
+// ----------------------------------------------------------------- geometry
+// Mesh and model constants passed by value to every kernel.
+struct Geo {
+  int dim;
+  int n[3];    // elements per axis (n[2] = 1 in 2-D)
+  int nn[3];   // nodes per axis (nn[2] = 1 in 2-D)
+  long long n_nodes;
+  long long n_elems;
+  double h[3];
+  double ih[3];  // 1/h
+  double jac;    // prod(h/2): Jacobian of the reference map
+  double dt, idt, eps4, lam, D, delta2;
+};
+
+Geo make_geo(const pf_params& p);
+
+// Element-loop modes of the residual kernel family.
+enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3 };
+
+// Launch helpers (defined in pf_residual.hip).
+int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
+                           const double* v, const double* F0, const double* eps_dev,
+                           double* out0, double* out1, double* gparams_partial,
+                           hipStream_t s);
+
+// ----------------------------------------------------------------- BLAS-1 (pf_blas.hip)
+// Deterministic reductions over n doubles: fixed grid, fixed order.
+int blas_dot(pf_problem* pb, const double* x, const double* y, long long n, double* out_dev,
+             hipStream_t s);
+int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const double* w,
+                  long long n, double* out_dev, hipStream_t s);
+int blas_axpy_dot(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
+                  double* w, long long n, double* dots_dev, int want_norm, hipStream_t s);
+int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
+                 double* x, long long n, hipStream_t s);
+int blas_scale_copy(const double* x, const double* alpha_dev, int invert, double* y,
+                    long long n, hipStream_t s);
+int blas_axpby(double a, const double* x, double b, const double* y, double* z, long long n,
+               hipStream_t s);
+int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, double* eps_dev,
+                hipStream_t s);
+int blas_reduce_partials(const double* partials, int nparts, int k, double* out_dev,
+                         double scale, hipStream_t s);
+int blas_sub_scalars(double* acc_dev, const double* x_dev, int k, hipStream_t s);
+
+// ----------------------------------------------------------------- preconditioner (pf_gmg.hip)
+struct GmgLevel;
+int pc_alloc(pf_problem* pb);
+hipError_t pc_free(pf_problem* pb);
+int pc_setup(pf_problem* pb, const double* U, int kind, int precision, hipStream_t s);
+int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s);
+
+// ----------------------------------------------------------------- misc kernels
+int misfit_launch(pf_problem* pb, const double* U, const double* target, double* L_dev,
+                  double* dLdU, hipStream_t s);
+
+}  // namespace pf
+
+// The opaque handle.
+struct pf_problem {
+  pf_params params;
+  pf::Geo geo;
+  int device;
+  long long n_dof;  // 2 * n_nodes
+  int gmres_m_max;
+
+  // reduction scratch: partial sums [k][n_red_blocks] and results
+  int n_red_blocks;
+  double* red_partials;  // (32 + 2) * n_red_blocks
+  double* red_out;       // 256 doubles of device results
+  double* host_pinned;   // 256 doubles of pinned host staging
+
+  // residual-family scratch
+  double* elem_buf;      // element contributions (element pass)
+  long long elem_buf_len;
+  double* vjp_partials;  // 2 * n_elem_blocks
+  int n_elem_blocks;
+  double* eps_dev;       // FD epsilon (device scalar)
+  double* tmp_vec[6];    // work vectors of n_dof doubles (kNumTmp)
+
+  // FGMRES basis
+  double* V;  // (m+1) * n_dof
+  double* Z;  // m * n_dof
+
+  // preconditioner state
+  int pc_kind;
+  int pc_precision;
+  void* pc;  // pf::PcState*
+};

@@ -1,0 +1,226 @@
+// Residual-family kernels: F(U), fused finite-difference Jv, analytic Jv and
+// the vector-Jacobian product, all from one element routine (pf_element.h).
+//
+// Two passes, both deterministic:
+//   k_elem   one thread per element: gathers its 2^d corner values (16-byte
+//            interleaved loads), evaluates the element vectors by sum
+//            factorisation and stores them structure-of-arrays,
+//            E[(o * 2^d + a) * n_elems + e];
+//   k_gather one thread per node: sums the contributions of the <= 2^d
+//            elements around it in a fixed order and writes the interleaved
+//            result (no atomics, no colouring).
+// The VJP's two parameter sums are reduced per block in a fixed tree and then
+// across blocks in a fixed order.
+#include "pf_element.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int kElemBlock = 256;
+
+template <int DIM>
+__device__ __forceinline__ void corner_nodes(const Geo& G, long long e, long long (&node)[1 << DIM]) {
+  const long long n0 = G.n[0], n1 = G.n[1];
+  const long long ex = e % n0;
+  const long long rest = e / n0;
+  const long long ey = (DIM == 2) ? rest : rest % n1;
+  const long long ez = (DIM == 2) ? 0 : rest / n1;
+  const long long s1 = G.nn[0], s2 = (long long)G.nn[0] * G.nn[1];
+  const long long base = ex + s1 * (ey + (long long)G.nn[1] * ez);
+#pragma unroll
+  for (int a = 0; a < (1 << DIM); ++a)
+    node[a] = base + (a & 1) + ((a >> 1) & 1) * s1 + (DIM == 3 ? ((a >> 2) & 1) * s2 : 0);
+}
+
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(kElemBlock)
+    k_elem(Geo G, const double2* __restrict__ U, const double2* __restrict__ Up,
+           const double2* __restrict__ V, const double* __restrict__ eps_dev,
+           double* __restrict__ E, double* __restrict__ vjp_part) {
+  constexpr int NA = 1 << DIM;
+  constexpr int NF = (MODE == MODE_RES || MODE == MODE_FD) ? 4 : 5;
+  constexpr int NO = (MODE == MODE_VJP) ? 4 : 2;
+  const long long e = (long long)blockIdx.x * kElemBlock + threadIdx.x;
+  const bool active = e < G.n_elems;
+  double ge = 0.0, gl = 0.0;
+  if (active) {
+    long long node[NA];
+    corner_nodes<DIM>(G, e, node);
+    double nod[NF][NA];
+    double eps = 0.0;
+    if (MODE == MODE_FD) eps = *eps_dev;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      double2 u = U[node[a]];
+      const double2 up = Up[node[a]];
+      if (MODE == MODE_FD) {
+        const double2 v = V[node[a]];
+        u.x = fma(eps, v.x, u.x);
+        u.y = fma(eps, v.y, u.y);
+      }
+      nod[0][a] = u.x;
+      nod[1][a] = u.y;
+      nod[2][a] = u.x - up.x;
+      if (MODE == MODE_RES || MODE == MODE_FD) {
+        nod[3][a] = u.y - up.y;
+      } else {
+        const double2 v = V[node[a]];
+        nod[3][a] = v.x;
+        nod[4][a] = v.y;
+      }
+    }
+    double out[NO][NA];
+    if (MODE == MODE_RES || MODE == MODE_FD) {
+      PhysResidual<DIM> ph(G);
+      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
+      else element_eval2<NF, NO>(nod, out, G, ph);
+    } else if (MODE == MODE_JVP) {
+      PhysJvp<DIM> ph(G);
+      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
+      else element_eval2<NF, NO>(nod, out, G, ph);
+    } else {
+      PhysVjp<DIM> ph(G);
+      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
+      else element_eval2<NF, NO>(nod, out, G, ph);
+      ge = ph.ge;
+      gl = ph.gl;
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) E[(long long)(o * NA + a) * G.n_elems + e] = out[o][a];
+  }
+  if (MODE == MODE_VJP) {
+    // fixed-order block reduction of the two parameter sums
+    __shared__ double red[2][kElemBlock];
+    red[0][threadIdx.x] = ge;
+    red[1][threadIdx.x] = gl;
+    __syncthreads();
+    for (int w = kElemBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + w];
+        red[1][threadIdx.x] += red[1][threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      vjp_part[blockIdx.x] = red[0][0];
+      vjp_part[gridDim.x + blockIdx.x] = red[1][0];
+    }
+  }
+}
+
+// Sum the element contributions around every node.  NO = 2 (one output
+// vector) or 4 (VJP: gU then gUprev).  mode FD: out0 = (sum - F0)/eps.
+template <int DIM, int NO>
+__global__ void __launch_bounds__(256)
+    k_gather(Geo G, const double* __restrict__ E, double2* __restrict__ out0,
+             double2* __restrict__ out1, const double2* __restrict__ F0,
+             const double* __restrict__ eps_dev, int fd) {
+  constexpr int NA = 1 << DIM;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.n_nodes) return;
+  const long long nn0 = G.nn[0], nn1 = G.nn[1];
+  const int ix = (int)(i % nn0);
+  const long long r = i / nn0;
+  const int iy = (DIM == 2) ? (int)r : (int)(r % nn1);
+  const int iz = (DIM == 2) ? 0 : (int)(r / nn1);
+  double acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+#pragma unroll
+  for (int bz = 0; bz < (DIM == 3 ? 2 : 1); ++bz) {
+    const int ez = iz - 1 + bz + (DIM == 3 ? 0 : 1);
+    if (DIM == 3 && (ez < 0 || ez >= G.n[2])) continue;
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const int ey = iy - 1 + by;
+      if (ey < 0 || ey >= G.n[1]) continue;
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int ex = ix - 1 + bx;
+        if (ex < 0 || ex >= G.n[0]) continue;
+        const long long e = ex + (long long)G.n[0] * (ey + (long long)G.n[1] * (DIM == 3 ? ez : 0));
+        const int a = (1 - bx) + 2 * (1 - by) + (DIM == 3 ? 4 * (1 - bz) : 0);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] += E[(long long)(o * NA + a) * G.n_elems + e];
+      }
+    }
+  }
+  if (fd) {
+    const double eps = *eps_dev;
+    const double2 f0 = F0[i];
+    double2 o;
+    if (eps == 0.0) {
+      o.x = 0.0;
+      o.y = 0.0;
+    } else {
+      const double ie = 1.0 / eps;
+      o.x = (acc[0] - f0.x) * ie;
+      o.y = (acc[1] - f0.y) * ie;
+    }
+    out0[i] = o;
+    return;
+  }
+  if (out0) out0[i] = make_double2(acc[0], acc[1]);
+  if (NO == 4 && out1) out1[i] = make_double2(acc[2 % NO], acc[3 % NO]);
+}
+
+template <int DIM>
+int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
+               const double* F0, const double* eps_dev, double* out0, double* out1,
+               double* vjp_part, hipStream_t s) {
+  const Geo& G = pb->geo;
+  const unsigned eb = (unsigned)((G.n_elems + kElemBlock - 1) / kElemBlock);
+  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
+  auto U2 = reinterpret_cast<const double2*>(U);
+  auto P2 = reinterpret_cast<const double2*>(Uprev);
+  auto V2 = reinterpret_cast<const double2*>(v);
+  switch (mode) {
+    case MODE_RES:
+      hipLaunchKernelGGL((k_elem<DIM, MODE_RES>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2,
+                         nullptr, nullptr, pb->elem_buf, nullptr);
+      break;
+    case MODE_FD:
+      hipLaunchKernelGGL((k_elem<DIM, MODE_FD>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
+                         eps_dev, pb->elem_buf, nullptr);
+      break;
+    case MODE_JVP:
+      hipLaunchKernelGGL((k_elem<DIM, MODE_JVP>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
+                         nullptr, pb->elem_buf, nullptr);
+      break;
+    default:
+      hipLaunchKernelGGL((k_elem<DIM, MODE_VJP>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
+                         nullptr, pb->elem_buf, vjp_part);
+      break;
+  }
+  PF_HIP_CHECK(hipGetLastError());
+  if (mode == MODE_VJP) {
+    hipLaunchKernelGGL((k_gather<DIM, 4>), dim3(nb), dim3(256), 0, s, G, pb->elem_buf,
+                       reinterpret_cast<double2*>(out0), reinterpret_cast<double2*>(out1),
+                       nullptr, nullptr, 0);
+  } else {
+    hipLaunchKernelGGL((k_gather<DIM, 2>), dim3(nb), dim3(256), 0, s, G, pb->elem_buf,
+                       reinterpret_cast<double2*>(out0), nullptr,
+                       reinterpret_cast<const double2*>(F0), eps_dev, mode == MODE_FD ? 1 : 0);
+  }
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+}  // namespace
+
+int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
+                           const double* v, const double* F0, const double* eps_dev,
+                           double* out0, double* out1, double* vjp_part, hipStream_t s) {
+  if (pb->geo.dim == 3)
+    return launch_dim<3>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+  return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+}
+
+int elem_blocks(const pf_problem* pb) {
+  return (int)((pb->geo.n_elems + kElemBlock - 1) / kElemBlock);
+}
+
+}  // namespace pf
