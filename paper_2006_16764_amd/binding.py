@@ -16,7 +16,7 @@ from typing import Optional
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpfjfnk.so")
+LIB_PATH = os.environ.get("PF_LIB", os.path.join(_PKG, "libpfjfnk.so"))
 
 PF_OK = 0
 PF_ERR_INVALID_ARG = -1

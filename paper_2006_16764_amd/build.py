@@ -4,7 +4,8 @@
 
 Each csrc/*.hip file is compiled with hipcc into _build/ and linked into
 paper_2006_16764_amd/libpfjfnk.so.  Packed FP32 instructions are disabled for
-all device code.
+all device code.  PF_HIPCC_FLAGS adds compiler flags (e.g. tuning macros),
+PF_LIB_OUT and PF_BUILD_TAG redirect the library and object names.
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(PKG, "libpfjfnk.so")
+LIB = os.environ.get("PF_LIB_OUT", os.path.join(PKG, "libpfjfnk.so"))
 ARCH = os.environ.get("PF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -35,6 +36,7 @@ def flags(debug: bool = False):
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
     f += ["-O1", "-g"] if debug else ["-O3"]
+    f += os.environ.get("PF_HIPCC_FLAGS", "").split()
     return f
 
 
@@ -43,7 +45,8 @@ def sources():
 
 
 def compile_one(src: str, debug: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    tag = os.environ.get("PF_BUILD_TAG", "")
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
     cmd = [hipcc()] + flags(debug) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -386,6 +386,9 @@ Geo make_geo(const pf_params& p) {
   G.lam = p.lambda;
   G.D = p.D;
   G.delta2 = p.delta2;
+  G.a0 = 1.0 - 3.0 * p.eps4;
+  G.e4x4 = 4.0 * p.eps4;
+  G.e16 = 16.0 * p.eps4;
   return G;
 }
 
@@ -443,11 +446,13 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   pb->n_red_blocks = (int)std::min<long long>(std::max<long long>(rb, 1), 1024);
   pb->n_elem_blocks = elem_blocks(pb);
   const int NA = 1 << pb->geo.dim;
-  pb->elem_buf_len = (long long)4 * NA * pb->geo.n_elems;
+  pb->elem_buf_len = pb->geo.dim == 2 ? (long long)4 * NA * pb->geo.n_elems : 1;
+  pb->side_len = pb->geo.dim == 3 ? fused3_side_len(pb->geo) : 1;
   if (hipMalloc(&pb->red_partials, (size_t)64 * pb->n_red_blocks * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->red_out, 512 * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&pb->host_pinned, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&pb->elem_buf, (size_t)pb->elem_buf_len * sizeof(double)) != hipSuccess ||
+      hipMalloc(&pb->side_buf, (size_t)pb->side_len * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->vjp_partials, (size_t)2 * pb->n_elem_blocks * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->eps_dev, 8 * sizeof(double)) != hipSuccess) {
     set_error("device allocation failed (workspace)");
@@ -485,9 +490,10 @@ int pf_destroy(pf_problem* pb) {
   chk(hipDeviceSynchronize(), "hipDeviceSynchronize");
   chk(pc_free(pb), "preconditioner buffers");
   double* bufs[] = {pb->red_partials, pb->red_out, pb->elem_buf, pb->vjp_partials, pb->eps_dev,
-                    pb->V, pb->Z};
-  const char* names[] = {"red_partials", "red_out", "elem_buf", "vjp_partials", "eps_dev", "V", "Z"};
-  for (int i = 0; i < 7; ++i)
+                    pb->V, pb->Z, pb->side_buf};
+  const char* names[] = {"red_partials", "red_out", "elem_buf", "vjp_partials", "eps_dev", "V", "Z",
+                         "side_buf"};
+  for (int i = 0; i < 8; ++i)
     if (bufs[i]) chk(hipFree(bufs[i]), names[i]);
   for (int i = 0; i < kNumTmp; ++i)
     if (pb->tmp_vec[i]) chk(hipFree(pb->tmp_vec[i]), "tmp_vec");

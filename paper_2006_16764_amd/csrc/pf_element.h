@@ -1,5 +1,5 @@
-// Q1 element evaluation by sum factorisation and the pointwise physics of the
-// coupled phase-field residual, its tangent and its adjoint.
+// Q1 element evaluation for the coupled phase-field residual, its tangent and
+// its adjoint.
 //
 // Reference element [-1,1]^d, corners a = ax + 2 ay (+ 4 az) at xi_k = -1 for
 // bit k = 0 and +1 for bit k = 1; 3 Gauss points per axis at -s, 0, s with
@@ -8,19 +8,35 @@
 //   B[g][0] = (1 - xi_g)/2,  B[g][1] = (1 + xi_g)/2,
 // and physical derivatives -1/h, +1/h (constant along the axis).
 //
-// element_eval interpolates NF nodal fields (value and gradient) to every
-// Gauss point plane by plane (z outermost, then y rows, then x points), calls
-// the pointwise functor, and contracts its NO outputs (s, f) with the test
-// functions:  out[o][a] += w_q (s_o N_a + f_o . grad N_a).
+// Split of the work:
+//  * nonlinear terms (anisotropic flux, a^2-weighted time term, lambda
+//    coupling) are integrated with the Gauss rule: quad3/quad2 interpolate the
+//    fields plane by plane (z outermost, then y rows, then x points), call the
+//    pointwise functor and contract its outputs with the test functions,
+//      out[o][a] += w_q (s_o N_a + f_o . grad N_a);
+//  * linear constant-coefficient terms (u equation, latent heat) are applied
+//    as the exact element mass and stiffness matrices in tensor-product form,
+//    M_e = M1 x M1 (x M1), K_e = sum over axes of K1 on that axis and M1 on
+//    the others, with M1 = h/6 [2 1; 1 2] and K1 = 1/h [1 -1; -1 1].  The
+//    3-point rule integrates these exactly, so both routes give the same
+//    discrete residual.
 #pragma once
 
 #include "pf_internal.h"
+
+// Unroll factor of the y-row loop of the 3-D Gauss rule (the z-plane loop is
+// not unrolled; the x-point loop is unrolled or not per physics functor,
+// kGxUnroll): a register-pressure / ILP trade-off.
+#ifndef PF_GY_UNROLL
+#define PF_GY_UNROLL 3
+#endif
+#define PF_PRAGMA(x) _Pragma(#x)
+#define PF_UNROLL(n) PF_PRAGMA(unroll n)
 
 namespace pf {
 
 struct Q1 {
   static constexpr double s = 0.77459666924148337704;  // sqrt(3/5)
-  // B[g][0] and B[g][1]: 1-D basis values at Gauss point g
   __host__ __device__ static constexpr double b0(int g) {
     return g == 0 ? 0.5 * (1.0 + s) : (g == 1 ? 0.5 : 0.5 * (1.0 - s));
   }
@@ -30,88 +46,167 @@ struct Q1 {
   __host__ __device__ static constexpr double w(int g) { return g == 1 ? 8.0 / 9.0 : 5.0 / 9.0; }
 };
 
-// ----------------------------------------------------------------- 3-D element
-template <int NF, int NO, class Phys>
-__device__ __forceinline__ void element_eval3(const double (&nod)[NF][8], double (&out)[NO][8],
-                                              const Geo& G, Phys& phys) {
+// ----------------------------------------------------------------- exact linear part
+// y += cm M_e xm + ck K_e xk, 3-D, corners a = ax + 2 ay + 4 az.
+__device__ __forceinline__ void mass_stiff3(const Geo& G, const double (&xm)[8], double cm,
+                                            const double (&xk)[8], double ck, double (&y)[8]) {
+  const double hx6 = G.h[0] / 6.0, hy6 = G.h[1] / 6.0, hz6 = G.h[2] / 6.0;
+  double t[8], c[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) t[a] = hx6 * (2.0 * xm[a] + xm[a ^ 1]);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) c[a] = hy6 * (2.0 * t[a] + t[a ^ 2]);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) y[a] += cm * (hz6 * (2.0 * c[a] + c[a ^ 4]));
+  // stiffness: Kx My Mz + Mx Ky Mz + Mx My Kz
+  double mx[8], kx[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    mx[a] = hx6 * (2.0 * xk[a] + xk[a ^ 1]);
+    kx[a] = (xk[a] - xk[a ^ 1]) * G.ih[0];
+  }
+  double mm[8], s2[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    mm[a] = hy6 * (2.0 * mx[a] + mx[a ^ 2]);                                 // Mx My
+    s2[a] = hy6 * (2.0 * kx[a] + kx[a ^ 2]) + (mx[a] - mx[a ^ 2]) * G.ih[1];  // Kx My + Mx Ky
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    y[a] += ck * (hz6 * (2.0 * s2[a] + s2[a ^ 4]) + (mm[a] - mm[a ^ 4]) * G.ih[2]);
+}
+
+__device__ __forceinline__ void mass_stiff2(const Geo& G, const double (&xm)[4], double cm,
+                                            const double (&xk)[4], double ck, double (&y)[4]) {
+  const double hx6 = G.h[0] / 6.0, hy6 = G.h[1] / 6.0;
+  double t[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) t[a] = hx6 * (2.0 * xm[a] + xm[a ^ 1]);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) y[a] += cm * (hy6 * (2.0 * t[a] + t[a ^ 2]));
+  double mx[4], kx[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    mx[a] = hx6 * (2.0 * xk[a] + xk[a ^ 1]);
+    kx[a] = (xk[a] - xk[a ^ 1]) * G.ih[0];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    y[a] += ck * (hy6 * (2.0 * kx[a] + kx[a ^ 2]) + (mx[a] - mx[a ^ 2]) * G.ih[1]);
+}
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (each step squares the relative error), used instead of the IEEE division
+// sequence in the pointwise physics.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ----------------------------------------------------------------- Gauss-rule part, 3-D
+// NG fields interpolated with value and gradient (ng), NV fields with value
+// only (nv); NS outputs with value and flux parts (os), NP value-only outputs
+// (op).  The functor is called as phys(gv, gg, vv, s, f, p) at every point and
+// phys.weight(w_q) right after.
+template <int NG, int NV, int NS, int NP, class Phys>
+__device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
+                                     const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS][8],
+                                     double (&op)[NP > 0 ? NP : 1][8], Phys& phys) {
   const double ihx = G.ih[0], ihy = G.ih[1], ihz = G.ih[2];
-#pragma unroll
-  for (int o = 0; o < NO; ++o)
-#pragma unroll
-    for (int a = 0; a < 8; ++a) out[o][a] = 0.0;
-
-  // z-derivatives of the nodal fields on the 4 (ax, ay) lines
-  double dz[NF][4];
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-#pragma unroll
-    for (int a = 0; a < 4; ++a) dz[f][a] = (nod[f][a + 4] - nod[f][a]) * ihz;
-
 #pragma unroll 1
   for (int gz = 0; gz < 3; ++gz) {
     const double bz0 = Q1::b0(gz), bz1 = Q1::b1(gz);
-    double pz[NF][4];  // field interpolated to the plane, at the 4 (ax, ay) corners
+    double pg[NG][4], dz[NG][4], pv[NV > 0 ? NV : 1][4];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NG; ++f)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) pz[f][a] = bz0 * nod[f][a] + bz1 * nod[f][a + 4];
-    double S[NO][4], Zc[NO][4];  // plane contraction accumulators
+      for (int a = 0; a < 4; ++a) {
+        pg[f][a] = bz0 * ng[f][a] + bz1 * ng[f][a + 4];
+        dz[f][a] = (ng[f][a + 4] - ng[f][a]) * ihz;
+      }
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
+    for (int f = 0; f < NV; ++f)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) { S[o][a] = 0.0; Zc[o][a] = 0.0; }
-
+      for (int a = 0; a < 4; ++a) pv[f][a] = bz0 * nv[f][a] + bz1 * nv[f][a + 4];
+    double S[NS][4], Zc[NS][4], P[NP > 0 ? NP : 1][4];
 #pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int o = 0; o < NS; ++o) S[o][a] = Zc[o][a] = 0.0;
+#pragma unroll
+      for (int o = 0; o < NP; ++o) P[o][a] = 0.0;
+    }
+PF_UNROLL(PF_GY_UNROLL)
     for (int gy = 0; gy < 3; ++gy) {
       const double by0 = Q1::b0(gy), by1 = Q1::b1(gy);
-      double qv[NF][2], qy[NF][2], qz[NF][2];
+      const double wrow = Q1::w(gy) * Q1::w(gz) * G.jac;
+      double qv[NG][2], qy[NG][2], qz[NG][2], qw[NV > 0 ? NV : 1][2];
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int ax = 0; ax < 2; ++ax) {
 #pragma unroll
-        for (int ax = 0; ax < 2; ++ax) {
-          qv[f][ax] = by0 * pz[f][ax] + by1 * pz[f][ax + 2];
-          qy[f][ax] = (pz[f][ax + 2] - pz[f][ax]) * ihy;
+        for (int f = 0; f < NG; ++f) {
+          qv[f][ax] = by0 * pg[f][ax] + by1 * pg[f][ax + 2];
+          qy[f][ax] = (pg[f][ax + 2] - pg[f][ax]) * ihy;
           qz[f][ax] = by0 * dz[f][ax] + by1 * dz[f][ax + 2];
         }
-      double rs[NO][2], rx[NO], ry[NO][2], rz[NO][2];  // row accumulators
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
+        for (int f = 0; f < NV; ++f) qw[f][ax] = by0 * pv[f][ax] + by1 * pv[f][ax + 2];
+      }
+      double rs[NS][2], rx[NS], ry[NS][2], rz[NS][2], rp[NP > 0 ? NP : 1][2];
+#pragma unroll
+      for (int o = 0; o < NS; ++o) {
         rx[o] = 0.0;
-#pragma unroll
-        for (int ax = 0; ax < 2; ++ax) { rs[o][ax] = 0.0; ry[o][ax] = 0.0; rz[o][ax] = 0.0; }
+        rs[o][0] = rs[o][1] = ry[o][0] = ry[o][1] = rz[o][0] = rz[o][1] = 0.0;
       }
 #pragma unroll
-      for (int gx = 0; gx < 3; ++gx) {
+      for (int o = 0; o < NP; ++o) rp[o][0] = rp[o][1] = 0.0;
+      auto point = [&](int gx) {
         const double bx0 = Q1::b0(gx), bx1 = Q1::b1(gx);
-        double v[NF], g[NF][3];
+        double gv[NG], gg[NG][3], vv[NV > 0 ? NV : 1];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          v[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
-          g[f][0] = (qv[f][1] - qv[f][0]) * ihx;
-          g[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
-          g[f][2] = bx0 * qz[f][0] + bx1 * qz[f][1];
+        for (int f = 0; f < NG; ++f) {
+          gv[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
+          gg[f][0] = (qv[f][1] - qv[f][0]) * ihx;
+          gg[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
+          gg[f][2] = bx0 * qz[f][0] + bx1 * qz[f][1];
         }
-        double s[NO], fl[NO][3];
-        phys(v, g, s, fl);
-        const double wq = Q1::w(gx) * Q1::w(gy) * Q1::w(gz) * G.jac;
+#pragma unroll
+        for (int f = 0; f < NV; ++f) vv[f] = bx0 * qw[f][0] + bx1 * qw[f][1];
+        double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
+        phys(gv, gg, vv, s, fl, p);
+        const double wq = Q1::w(gx) * wrow;
+        const double w0 = wq * bx0, w1 = wq * bx1;
         phys.weight(wq);
 #pragma unroll
-        for (int o = 0; o < NO; ++o) {
-          const double ws = wq * s[o], wx = wq * fl[o][0], wy = wq * fl[o][1], wz = wq * fl[o][2];
-          rs[o][0] += ws * bx0;
-          rs[o][1] += ws * bx1;
-          rx[o] += wx;
-          ry[o][0] += wy * bx0;
-          ry[o][1] += wy * bx1;
-          rz[o][0] += wz * bx0;
-          rz[o][1] += wz * bx1;
+        for (int o = 0; o < NS; ++o) {
+          rs[o][0] = fma(s[o], w0, rs[o][0]);
+          rs[o][1] = fma(s[o], w1, rs[o][1]);
+          rx[o] = fma(fl[o][0], wq, rx[o]);
+          ry[o][0] = fma(fl[o][1], w0, ry[o][0]);
+          ry[o][1] = fma(fl[o][1], w1, ry[o][1]);
+          rz[o][0] = fma(fl[o][2], w0, rz[o][0]);
+          rz[o][1] = fma(fl[o][2], w1, rz[o][1]);
         }
-      }
-      // contract the row in y: corners (ax, ay) -> index ax + 2 ay
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        const double sx0 = rs[o][0] - rx[o] * ihx;  // s N + f_x dN/dx for ax = 0
-        const double sx1 = rs[o][1] + rx[o] * ihx;  // ax = 1
+        for (int o = 0; o < NP; ++o) {
+          rp[o][0] = fma(p[o], w0, rp[o][0]);
+          rp[o][1] = fma(p[o], w1, rp[o][1]);
+        }
+            };
+      if constexpr (Phys::kGxUnroll == 1) {
+#pragma unroll 1
+        for (int gx = 0; gx < 3; ++gx) point(gx);
+      } else {
+#pragma unroll
+        for (int gx = 0; gx < 3; ++gx) point(gx);
+      }
+#pragma unroll
+      for (int o = 0; o < NS; ++o) {
+        const double sx0 = rs[o][0] - rx[o] * ihx;
+        const double sx1 = rs[o][1] + rx[o] * ihx;
         S[o][0] += by0 * sx0 - ry[o][0] * ihy;
         S[o][1] += by0 * sx1 - ry[o][1] * ihy;
         S[o][2] += by1 * sx0 + ry[o][0] * ihy;
@@ -121,77 +216,105 @@ __device__ __forceinline__ void element_eval3(const double (&nod)[NF][8], double
         Zc[o][2] += by1 * rz[o][0];
         Zc[o][3] += by1 * rz[o][1];
       }
-    }
-    // contract the plane in z
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        out[o][a] += bz0 * S[o][a] - Zc[o][a] * ihz;
-        out[o][a + 4] += bz1 * S[o][a] + Zc[o][a] * ihz;
+      for (int o = 0; o < NP; ++o) {
+        P[o][0] += by0 * rp[o][0];
+        P[o][1] += by0 * rp[o][1];
+        P[o][2] += by1 * rp[o][0];
+        P[o][3] += by1 * rp[o][1];
       }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int o = 0; o < NS; ++o) {
+        os[o][a] += bz0 * S[o][a] - Zc[o][a] * ihz;
+        os[o][a + 4] += bz1 * S[o][a] + Zc[o][a] * ihz;
+      }
+#pragma unroll
+      for (int o = 0; o < NP; ++o) {
+        op[o][a] += bz0 * P[o][a];
+        op[o][a + 4] += bz1 * P[o][a];
+      }
+    }
   }
 }
 
-// ----------------------------------------------------------------- 2-D element
-template <int NF, int NO, class Phys>
-__device__ __forceinline__ void element_eval2(const double (&nod)[NF][4], double (&out)[NO][4],
-                                              const Geo& G, Phys& phys) {
+// ----------------------------------------------------------------- Gauss-rule part, 2-D
+template <int NG, int NV, int NS, int NP, class Phys>
+__device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
+                                     const double (&nv)[NV > 0 ? NV : 1][4], double (&os)[NS][4],
+                                     double (&op)[NP > 0 ? NP : 1][4], Phys& phys) {
   const double ihx = G.ih[0], ihy = G.ih[1];
-#pragma unroll
-  for (int o = 0; o < NO; ++o)
-#pragma unroll
-    for (int a = 0; a < 4; ++a) out[o][a] = 0.0;
 #pragma unroll
   for (int gy = 0; gy < 3; ++gy) {
     const double by0 = Q1::b0(gy), by1 = Q1::b1(gy);
-    double qv[NF][2], qy[NF][2];
+    double qv[NG][2], qy[NG][2], qw[NV > 0 ? NV : 1][2];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int ax = 0; ax < 2; ++ax) {
 #pragma unroll
-      for (int ax = 0; ax < 2; ++ax) {
-        qv[f][ax] = by0 * nod[f][ax] + by1 * nod[f][ax + 2];
-        qy[f][ax] = (nod[f][ax + 2] - nod[f][ax]) * ihy;
+      for (int f = 0; f < NG; ++f) {
+        qv[f][ax] = by0 * ng[f][ax] + by1 * ng[f][ax + 2];
+        qy[f][ax] = (ng[f][ax + 2] - ng[f][ax]) * ihy;
       }
-    double rs[NO][2], rx[NO], ry[NO][2];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
+      for (int f = 0; f < NV; ++f) qw[f][ax] = by0 * nv[f][ax] + by1 * nv[f][ax + 2];
+    }
+    double rs[NS][2], rx[NS], ry[NS][2], rp[NP > 0 ? NP : 1][2];
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
       rx[o] = 0.0;
       rs[o][0] = rs[o][1] = ry[o][0] = ry[o][1] = 0.0;
     }
 #pragma unroll
+    for (int o = 0; o < NP; ++o) rp[o][0] = rp[o][1] = 0.0;
+#pragma unroll
     for (int gx = 0; gx < 3; ++gx) {
       const double bx0 = Q1::b0(gx), bx1 = Q1::b1(gx);
-      double v[NF], g[NF][3];
+      double gv[NG], gg[NG][3], vv[NV > 0 ? NV : 1];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        v[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
-        g[f][0] = (qv[f][1] - qv[f][0]) * ihx;
-        g[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
-        g[f][2] = 0.0;
+      for (int f = 0; f < NG; ++f) {
+        gv[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
+        gg[f][0] = (qv[f][1] - qv[f][0]) * ihx;
+        gg[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
+        gg[f][2] = 0.0;
       }
-      double s[NO], fl[NO][3];
-      phys(v, g, s, fl);
+#pragma unroll
+      for (int f = 0; f < NV; ++f) vv[f] = bx0 * qw[f][0] + bx1 * qw[f][1];
+      double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
+      phys(gv, gg, vv, s, fl, p);
       const double wq = Q1::w(gx) * Q1::w(gy) * G.jac;
+      const double w0 = wq * bx0, w1 = wq * bx1;
       phys.weight(wq);
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        const double ws = wq * s[o], wx = wq * fl[o][0], wy = wq * fl[o][1];
-        rs[o][0] += ws * bx0;
-        rs[o][1] += ws * bx1;
-        rx[o] += wx;
-        ry[o][0] += wy * bx0;
-        ry[o][1] += wy * bx1;
+      for (int o = 0; o < NS; ++o) {
+        rs[o][0] = fma(s[o], w0, rs[o][0]);
+        rs[o][1] = fma(s[o], w1, rs[o][1]);
+        rx[o] = fma(fl[o][0], wq, rx[o]);
+        ry[o][0] = fma(fl[o][1], w0, ry[o][0]);
+        ry[o][1] = fma(fl[o][1], w1, ry[o][1]);
+      }
+#pragma unroll
+      for (int o = 0; o < NP; ++o) {
+        rp[o][0] = fma(p[o], w0, rp[o][0]);
+        rp[o][1] = fma(p[o], w1, rp[o][1]);
       }
     }
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
+    for (int o = 0; o < NS; ++o) {
       const double sx0 = rs[o][0] - rx[o] * ihx;
       const double sx1 = rs[o][1] + rx[o] * ihx;
-      out[o][0] += by0 * sx0 - ry[o][0] * ihy;
-      out[o][1] += by0 * sx1 - ry[o][1] * ihy;
-      out[o][2] += by1 * sx0 + ry[o][0] * ihy;
-      out[o][3] += by1 * sx1 + ry[o][1] * ihy;
+      os[o][0] += by0 * sx0 - ry[o][0] * ihy;
+      os[o][1] += by0 * sx1 - ry[o][1] * ihy;
+      os[o][2] += by1 * sx0 + ry[o][0] * ihy;
+      os[o][3] += by1 * sx1 + ry[o][1] * ihy;
+    }
+#pragma unroll
+    for (int o = 0; o < NP; ++o) {
+      op[o][0] += by0 * rp[o][0];
+      op[o][1] += by0 * rp[o][1];
+      op[o][2] += by1 * rp[o][0];
+      op[o][3] += by1 * rp[o][1];
     }
   }
 }
@@ -203,7 +326,8 @@ __device__ __forceinline__ void element_eval2(const double (&nod)[NF][4], double
 template <int DIM>
 struct Aniso {
   double q, S, iQ, a, da[3], J[3];
-  __device__ __forceinline__ void eval(const double* g, double eps4, double delta2) {
+  // full evaluation (a, da/dg and J)
+  __device__ __forceinline__ void eval(const double* g, const Geo& G) {
     double g2[3];
     q = 0.0;
     S = 0.0;
@@ -211,25 +335,44 @@ struct Aniso {
     for (int k = 0; k < DIM; ++k) {
       g2[k] = g[k] * g[k];
       q += g2[k];
-      S += g2[k] * g2[k];
+      S = fma(g2[k], g2[k], S);
     }
-    const double Q = q + delta2;
-    iQ = 1.0 / Q;
+    iQ = rcp_nr(q + G.delta2);
     const double iQ2 = iQ * iQ;
-    a = 1.0 - 3.0 * eps4 + 4.0 * eps4 * S * iQ2;
+    a = fma(G.e4x4 * S, iQ2, G.a0);
     const double SQ = S * iQ;
-    const double c = 16.0 * eps4 * iQ2;
-    const double a2 = a * a, aq = a * q;
+    const double c = G.e16 * iQ2;
+    const double a2 = a * a, aqc = a * q * c;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      da[k] = c * g[k] * (g2[k] - SQ);
-      J[k] = a2 * g[k] + aq * da[k];
+      const double t = g2[k] - SQ;
+      da[k] = c * g[k] * t;
+      J[k] = g[k] * fma(aqc, t, a2);
     }
+  }
+  // a and J only: J_k = g_k (a^2 + a q 16 eps4 (g_k^2 - S/Q)/Q^2)
+  __device__ __forceinline__ void flux(const double* g, const Geo& G) {
+    double g2[3];
+    q = 0.0;
+    S = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      g2[k] = g[k] * g[k];
+      q += g2[k];
+      S = fma(g2[k], g2[k], S);
+    }
+    iQ = rcp_nr(q + G.delta2);
+    const double iQ2 = iQ * iQ;
+    a = fma(G.e4x4 * S, iQ2, G.a0);
+    const double SQ = S * iQ;
+    const double a2 = a * a, aqc = a * q * (G.e16 * iQ2);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) J[k] = g[k] * fma(aqc, g2[k] - SQ, a2);
   }
   // H v with H the Hessian of a^2 |g|^2 / 2:
   // H v = a^2 v + 2a (g (da.v) + da (g.v)) + q da (da.v) + a q 4 eps4 T v,
   // T v = 12 g^2 v/Q^2 - 16 (g^3 (g.v) + g (g^3.v))/Q^3 - 4 S v/Q^3 + 24 S g (g.v)/Q^4.
-  __device__ __forceinline__ void hess(const double* g, const double* v, double eps4,
+  __device__ __forceinline__ void hess(const double* g, const double* v, double e4x4,
                                        double* Hv) const {
     double gv = 0.0, dav = 0.0, g3v = 0.0;
 #pragma unroll
@@ -240,7 +383,7 @@ struct Aniso {
     }
     const double iQ2 = iQ * iQ, iQ3 = iQ2 * iQ, iQ4 = iQ2 * iQ2;
     const double a2 = a * a;
-    const double c4 = 4.0 * eps4 * a * q;
+    const double c4 = e4x4 * a * q;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const double gk = g[k];
@@ -251,88 +394,89 @@ struct Aniso {
   }
 };
 
-// Residual: fields {phi, u, phi - phi^n, u - u^n}; outputs {F1, F2}.
+// Residual F1 (Gauss part): gradient field {phi}; value fields {u, phi - phi^n};
+// output s = a^2 (phi - phi^n)/dt - (phi - phi^3 - lambda (1 - phi^2)^2 u), f = J.
 template <int DIM>
 struct PhysResidual {
+  static constexpr int kGxUnroll = 1;
   const Geo& G;
   __device__ PhysResidual(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}
-  __device__ __forceinline__ void operator()(const double* v, const double (*g)[3], double* s,
-                                             double (*f)[3]) {
-    const double phi = v[0], u = v[1], dphi = v[2], du = v[3];
+  // vv[1] holds (phi - phi^n)/dt
+  __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
+                                             const double* vv, double* s, double (*f)[3],
+                                             double*) {
+    const double phi = gv[0], u = vv[0], dphi_dt = vv[1];
     Aniso<DIM> A;
-    A.eval(g[0], G.eps4, G.delta2);
-    const double p2 = phi * phi;
-    const double om = 1.0 - p2;
-    const double R = phi - p2 * phi - G.lam * om * om * u;
-    s[0] = A.a * A.a * dphi * G.idt - R;
-    s[1] = (du - 0.5 * dphi) * G.idt;
+    A.flux(gg[0], G);
+    const double om = fma(-phi, phi, 1.0);
+    const double R = om * fma(-G.lam * om, u, phi);  // phi - phi^3 - lambda (1-phi^2)^2 u
+    s[0] = fma(A.a * A.a, dphi_dt, -R);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      f[0][k] = (k < DIM) ? A.J[k] : 0.0;
-      f[1][k] = (k < DIM) ? G.D * g[1][k] : 0.0;
-    }
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? A.J[k] : 0.0;
   }
 };
 
-// Tangent: fields {phi, u, phi - phi^n, dphi_tan, du_tan}; outputs {J1 v, J2 v}.
+// Tangent of F1 (Gauss part): gradient fields {phi, v_phi}; value fields
+// {u, phi - phi^n, v_u}.
 template <int DIM>
 struct PhysJvp {
+  static constexpr int kGxUnroll = 3;
   const Geo& G;
   __device__ PhysJvp(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}
-  __device__ __forceinline__ void operator()(const double* v, const double (*g)[3], double* s,
-                                             double (*f)[3]) {
-    const double phi = v[0], u = v[1], dphi = v[2], tp = v[3], tu = v[4];
+  __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
+                                             const double* vv, double* s, double (*f)[3],
+                                             double*) {
+    const double phi = gv[0], tp = gv[1], u = vv[0], dphi = vv[1], tu = vv[2];
     Aniso<DIM> A;
-    A.eval(g[0], G.eps4, G.delta2);
+    A.eval(gg[0], G);
     double dav = 0.0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) dav += A.da[k] * g[3][k];
+    for (int k = 0; k < DIM; ++k) dav += A.da[k] * gg[1][k];
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;  // dR/dphi
     const double Ru = -G.lam * om * om;                              // dR/du
     s[0] = (2.0 * A.a * dav * dphi + A.a * A.a * tp) * G.idt - (Rp * tp + Ru * tu);
-    s[1] = (tu - 0.5 * tp) * G.idt;
     double Hv[3] = {0.0, 0.0, 0.0};
-    A.hess(g[0], g[3], G.eps4, Hv);
+    A.hess(gg[0], gg[1], G.e4x4, Hv);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      f[0][k] = (k < DIM) ? Hv[k] : 0.0;
-      f[1][k] = (k < DIM) ? G.D * g[4][k] : 0.0;
-    }
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hv[k] : 0.0;
   }
 };
 
-// Adjoint: fields {phi, u, phi - phi^n, w1, w2}; outputs {gU_phi, gU_u,
-// gUprev_phi, gUprev_u}; accumulates w . dF/d eps4 and w . dF/d lambda.
+// Adjoint of F1 (Gauss part): gradient fields {phi, w1}; value fields
+// {u, phi - phi^n}; outputs: gU_phi (value + flux), value-only gU_u (lambda
+// term) and gUprev_phi (time term); accumulates w1 . dF1/d eps4 and
+// w1 . dF1/d lambda (F2 does not depend on the parameters).
 template <int DIM>
 struct PhysVjp {
+  static constexpr int kGxUnroll = 3;
   const Geo& G;
-  double ge, gl;      // element accumulators
-  double pe, pl;      // pointwise values (weighted in weight())
+  double ge, gl;  // element accumulators
+  double pe, pl;  // pointwise values (weighted in weight())
   __device__ PhysVjp(const Geo& g) : G(g), ge(0.0), gl(0.0), pe(0.0), pl(0.0) {}
   __device__ __forceinline__ void weight(double wq) {
     ge += wq * pe;
     gl += wq * pl;
   }
-  __device__ __forceinline__ void operator()(const double* v, const double (*g)[3], double* s,
-                                             double (*f)[3]) {
-    const double phi = v[0], u = v[1], dphi = v[2], w1 = v[3], w2 = v[4];
+  __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
+                                             const double* vv, double* s, double (*f)[3],
+                                             double* p) {
+    const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
     Aniso<DIM> A;
-    A.eval(g[0], G.eps4, G.delta2);
+    A.eval(gg[0], G);
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
     const double a2 = A.a * A.a;
     double Hw[3] = {0.0, 0.0, 0.0};
-    A.hess(g[0], g[3], G.eps4, Hw);
+    A.hess(gg[0], gg[1], G.e4x4, Hw);
     const double m = 2.0 * A.a * dphi * G.idt * w1;  // d(a^2 dphi/dt w1)/da
-    s[0] = w1 * (a2 * G.idt - Rp) - 0.5 * w2 * G.idt;
-    s[1] = w1 * G.lam * om * om + w2 * G.idt;
-    s[2] = -w1 * a2 * G.idt + 0.5 * w2 * G.idt;
-    s[3] = -w2 * G.idt;
+    s[0] = w1 * (a2 * G.idt - Rp);
+    p[0] = w1 * G.lam * om * om;
+    p[1] = -w1 * a2 * G.idt;
     // parameter derivatives: da/deps4 = -3 + 4 S/Q^2, d(da)/deps4 = da/eps4
     const double iQ2 = A.iQ * A.iQ;
     const double ae = -3.0 + 4.0 * A.S * iQ2;
@@ -340,19 +484,121 @@ struct PhysVjp {
     double Je_w = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double gk = g[0][k];
+      const double gk = gg[0][k];
       const double dae = 16.0 * iQ2 * gk * (gk * gk - SQ);
       const double Je = 2.0 * A.a * ae * gk + ae * A.q * A.da[k] + A.a * A.q * dae;
-      Je_w += Je * g[3][k];
+      Je_w += Je * gg[1][k];
     }
     pe = m * ae + Je_w;
     pl = w1 * om * om * u;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      f[0][k] = (k < DIM) ? Hw[k] + m * A.da[k] : 0.0;
-      f[1][k] = (k < DIM) ? G.D * g[4][k] : 0.0;
-      f[2][k] = 0.0;
-      f[3][k] = 0.0;
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hw[k] + m * A.da[k] : 0.0;
+  }
+};
+
+// ----------------------------------------------------------------- whole-element routine
+// Corner values (a = 0 .. 2^DIM - 1): u0/u1 = (phi, u) of the state, p0/p1 =
+// (phi^n, u^n), v0/v1 = direction (JVP) or cotangent (VJP) parts.  For the FD
+// product the caller passes the perturbed state as u0/u1.  out[0..1][a] are the
+// two fields of the output vector; for the VJP out[2..3][a] those of gUprev.
+template <int DIM, int MODE>
+struct Element {
+  static constexpr int NA = 1 << DIM;
+  static constexpr int NO = MODE == MODE_VJP ? 4 : 2;
+
+  template <int NG, int NV, int NS, int NP, class Phys>
+  __device__ __forceinline__ static void quad(const Geo& G, const double (&ng)[NG][NA],
+                                              const double (&nv)[NV][NA], double (&os)[NS][NA],
+                                              double (&op)[NP > 0 ? NP : 1][NA], Phys& ph) {
+    if constexpr (DIM == 3) quad3<NG, NV, NS, NP>(G, ng, nv, os, op, ph);
+    else quad2<NG, NV, NS, NP>(G, ng, nv, os, op, ph);
+  }
+
+  __device__ __forceinline__ static void lin(const Geo& G, const double (&xm)[NA], double cm,
+                                             const double (&xk)[NA], double ck, double (&y)[NA]) {
+    if constexpr (DIM == 3) mass_stiff3(G, xm, cm, xk, ck, y);
+    else mass_stiff2(G, xm, cm, xk, ck, y);
+  }
+
+  __device__ __forceinline__ static void run(const Geo& G, const double (&u0)[NA],
+                                             const double (&u1)[NA], const double (&p0)[NA],
+                                             const double (&p1)[NA], const double (&v0)[NA],
+                                             const double (&v1)[NA], double (&out)[NO][NA],
+                                             double& ge, double& gl) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) out[o][a] = 0.0;
+    double dphi[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) dphi[a] = u0[a] - p0[a];
+    double dummy[1][NA];
+    if constexpr (MODE == MODE_RES || MODE == MODE_FD) {
+      // F2 = M (du - dphi/2)/dt + D K u
+      double y[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) y[a] = (u1[a] - p1[a]) - 0.5 * dphi[a];
+      lin(G, y, G.idt, u1, G.D, out[1]);
+      double ngv[1][NA], nvv[2][NA], os[1][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        ngv[0][a] = u0[a];
+        nvv[0][a] = u1[a];
+        nvv[1][a] = dphi[a] * G.idt;
+        os[0][a] = 0.0;
+      }
+      PhysResidual<DIM> ph(G);
+      quad<1, 2, 1, 0>(G, ngv, nvv, os, dummy, ph);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+    } else if constexpr (MODE == MODE_JVP) {
+      // d F2 = M (v_u - v_phi/2)/dt + D K v_u
+      double y[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) y[a] = v1[a] - 0.5 * v0[a];
+      lin(G, y, G.idt, v1, G.D, out[1]);
+      double ngv[2][NA], nvv[3][NA], os[1][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        ngv[0][a] = u0[a];
+        ngv[1][a] = v0[a];
+        nvv[0][a] = u1[a];
+        nvv[1][a] = dphi[a];
+        nvv[2][a] = v1[a];
+        os[0][a] = 0.0;
+      }
+      PhysJvp<DIM> ph(G);
+      quad<2, 3, 1, 0>(G, ngv, nvv, os, dummy, ph);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+    } else {
+      // F2 part of the adjoint (M, K symmetric): gU_phi -= M w2/(2dt),
+      // gU_u += M w2/dt + D K w2, gUprev_phi += M w2/(2dt), gUprev_u -= M w2/dt
+      double zero[NA], mw[NA], kw[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) zero[a] = mw[a] = kw[a] = 0.0;
+      lin(G, v1, 1.0, zero, 0.0, mw);
+      lin(G, zero, 0.0, v1, G.D, kw);
+      double ngv[2][NA], nvv[2][NA], os[1][NA], op[2][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        ngv[0][a] = u0[a];
+        ngv[1][a] = v0[a];
+        nvv[0][a] = u1[a];
+        nvv[1][a] = dphi[a];
+        os[0][a] = op[0][a] = op[1][a] = 0.0;
+      }
+      PhysVjp<DIM> ph(G);
+      quad<2, 2, 1, 2>(G, ngv, nvv, os, op, ph);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        out[0][a] = os[0][a] - 0.5 * G.idt * mw[a];
+        out[1][a] = op[0][a] + G.idt * mw[a] + kw[a];
+        out[2][a] = op[1][a] + 0.5 * G.idt * mw[a];
+        out[3][a] = -G.idt * mw[a];
+      }
+      ge = ph.ge;
+      gl = ph.gl;
     }
   }
 };

@@ -1,0 +1,347 @@
+// Single-pass 3-D residual family (F, fused FD Jv, analytic Jv, VJP).
+//
+// A workgroup of 256 lanes owns a tile of 16 x 16 element columns and marches
+// through KZ element layers in z.  Per layer it stages the next node plane
+// (17 x 17 nodes of U, U^n and the direction/cotangent V; for the FD product
+// the perturbed state U + eps V) in LDS, every lane evaluates one element
+// (pf_element.h) and the node sums are formed in LDS in a fixed order:
+//   plane k = (top contributions of layer k-1, carried in registers)
+//           + (bottom contributions of layer k).
+// Nodes strictly inside the tile box are complete and written once.  Nodes on
+// the tile's side faces or on its first/last plane also receive contributions
+// from neighbouring tiles; their partial sums go to a side buffer indexed by
+// (tile, local node) and k_fixup3 adds the partials of the <= 8 tiles that
+// share such a node, in a fixed tile order.  No atomics: results are bitwise
+// reproducible.
+#include "pf_element.h"
+
+namespace pf {
+
+namespace {
+
+constexpr int TX = 16, TY = 16, KZ = 16;
+constexpr int PX = TX + 1, PY = TY + 1;
+constexpr int PN = PX * PY;  // nodes per staged plane
+constexpr int kThreads = TX * TY;
+
+struct Tiles {
+  int ntx, nty, ntz;
+};
+
+template <int MODE>
+struct ModeInfo {
+  static constexpr bool kHasV = MODE != MODE_RES;
+  static constexpr int NO = MODE == MODE_VJP ? 4 : 2;  // doubles per node output
+};
+
+__device__ __forceinline__ long long gnode(const Geo& G, int x, int y, int z) {
+  return x + (long long)G.nn[0] * (y + (long long)G.nn[1] * z);
+}
+
+// Residual and FD product fit 2 waves per SIMD without spilling; the tangent
+// and adjoint need the whole register file of one wave.
+template <int MODE>
+__global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD) ? 2 : 1)
+    k_fused3(Geo G, Tiles T, const double2* __restrict__ U, const double2* __restrict__ Up,
+             const double2* __restrict__ V, const double* __restrict__ eps_dev,
+             const double2* __restrict__ F0, double2* __restrict__ out0, double2* __restrict__ out1,
+             double* __restrict__ side, double* __restrict__ vjp_part) {
+  using MI = ModeInfo<MODE>;
+  constexpr int NO = MI::NO;
+  __shared__ double2 su[2][PN];
+  __shared__ double2 sp[2][PN];
+  __shared__ double2 sv[MI::kHasV && MODE != MODE_FD ? 2 : 1][MI::kHasV && MODE != MODE_FD ? PN : 1];
+  __shared__ double cb[NO][4][kThreads];
+
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int tx = tile % T.ntx;
+  const int ty = (tile / T.ntx) % T.nty;
+  const int tz = tile / (T.ntx * T.nty);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * KZ;
+  const int lxmax = min(TX, G.n[0] - x0);  // last local node index in x
+  const int lymax = min(TY, G.n[1] - y0);
+  const int kzmax = min(KZ, G.n[2] - z0);  // element layers in this chunk
+  const int ei = tid % TX, ej = tid / TX;  // this lane's element column
+  const bool has_elem = ei < lxmax && ej < lymax;
+  const double eps = (MODE == MODE_FD) ? *eps_dev : 0.0;
+
+  // node ownership for the gathers: lane owns node tid and, for tid < PN - 256, node 256 + tid
+  constexpr int kSecond = PN - kThreads;  // 33
+  const int nA = tid, nB = tid + kThreads;
+  const bool ownB = tid < kSecond;
+  double carryA[NO], carryB[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) carryA[o] = carryB[o] = 0.0;
+
+  auto load_plane = [&](int slot, int z) {
+    for (int n = tid; n < PN; n += kThreads) {
+      const int lx = n % PX, ly = n / PX;
+      if (lx <= lxmax && ly <= lymax) {
+        const long long g = gnode(G, x0 + lx, y0 + ly, z);
+        double2 u = U[g];
+        if (MODE == MODE_FD) {
+          const double2 v = V[g];
+          u.x = fma(eps, v.x, u.x);
+          u.y = fma(eps, v.y, u.y);
+        } else if (MI::kHasV) {
+          sv[slot][n] = V[g];
+        }
+        su[slot][n] = u;
+        sp[slot][n] = Up[g];
+      }
+    }
+  };
+
+  const long long tile_base = (long long)tile * (KZ + 1) * PN;
+  // Write the sum of node n (local) of plane lz: final value or side-buffer partial.
+  auto emit = [&](int n, int lz, const double* acc) {
+    const int lx = n % PX, ly = n / PX;
+    if (lx > lxmax || ly > lymax) return;
+    const bool ring = lx == 0 || lx == lxmax || ly == 0 || ly == lymax || lz == 0 || lz == kzmax;
+    if (ring) {
+      double* s = side + (tile_base + (long long)lz * PN + n) * NO;
+#pragma unroll
+      for (int o = 0; o < NO; ++o) s[o] = acc[o];
+      return;
+    }
+    const long long g = gnode(G, x0 + lx, y0 + ly, z0 + lz);
+    if (MODE == MODE_FD) {
+      const double2 f0 = F0[g];
+      const double ie = eps == 0.0 ? 0.0 : 1.0 / eps;
+      out0[g] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
+    } else {
+      if (out0) out0[g] = make_double2(acc[0], acc[1]);
+      if (NO == 4 && out1) out1[g] = make_double2(acc[2 % NO], acc[3 % NO]);
+    }
+  };
+
+  // Sum of corner half h (0 = bottom corners a = 0..3, 1 = top a = 4..7) of the
+  // <= 4 in-plane elements around local node n.
+  auto gather = [&](int n, double* acc) {
+    const int lx = n % PX, ly = n / PX;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      const int e_j = ly - 1 + by;
+      if (e_j < 0 || e_j >= lymax) continue;
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int e_i = lx - 1 + bx;
+        if (e_i < 0 || e_i >= lxmax) continue;
+        const int lane = e_i + TX * e_j;
+        const int a = (1 - bx) + 2 * (1 - by);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] += cb[o][a][lane];
+      }
+    }
+  };
+
+  double ge = 0.0, gl = 0.0;
+  load_plane(0, z0);
+  for (int kz = 0; kz < kzmax; ++kz) {
+    const int bot = kz & 1, top = bot ^ 1;
+    load_plane(top, z0 + kz + 1);
+    __syncthreads();
+    double out[NO][8];
+    if (has_elem) {
+      double u0[8], u1[8], p0[8], p1[8], v0[8], v1[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int slot = (a & 4) ? top : bot;
+        const int n = (ei + (a & 1)) + PX * (ej + ((a >> 1) & 1));
+        const double2 u = su[slot][n];
+        const double2 up = sp[slot][n];
+        u0[a] = u.x;
+        u1[a] = u.y;
+        p0[a] = up.x;
+        p1[a] = up.y;
+        if (MODE == MODE_JVP || MODE == MODE_VJP) {
+          const double2 v = sv[slot][n];
+          v0[a] = v.x;
+          v1[a] = v.y;
+        } else {
+          v0[a] = v1[a] = 0.0;
+        }
+      }
+      double eg = 0.0, lg = 0.0;
+      Element<3, MODE>::run(G, u0, u1, p0, p1, v0, v1, out, eg, lg);
+      ge += eg;
+      gl += lg;
+    } else {
+#pragma unroll
+      for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) out[o][a] = 0.0;
+    }
+    // bottom corners -> plane kz
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) cb[o][a][tid] = out[o][a];
+    __syncthreads();
+    {
+      double acc[NO];
+      gather(nA, acc);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) acc[o] += carryA[o];
+      emit(nA, kz, acc);
+      if (ownB) {
+        gather(nB, acc);
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] += carryB[o];
+        emit(nB, kz, acc);
+      }
+    }
+    __syncthreads();
+    // top corners -> carried to plane kz + 1
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) cb[o][a][tid] = out[o][a + 4];
+    __syncthreads();
+    gather(nA, carryA);
+    if (ownB) gather(nB, carryB);
+    __syncthreads();
+  }
+  emit(nA, kzmax, carryA);
+  if (ownB) emit(nB, kzmax, carryB);
+
+  if (MODE == MODE_VJP) {
+    // fixed-order block reduction of the parameter sums (cb reused as scratch)
+    double* red = &cb[0][0][0];
+    red[tid] = ge;
+    red[kThreads + tid] = gl;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[tid] += red[tid + w];
+        red[kThreads + tid] += red[kThreads + tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      vjp_part[tile] = red[0];
+      vjp_part[gridDim.x + tile] = red[kThreads];
+    }
+  }
+}
+
+// Tiles containing coordinate c along an axis with tile width w, tile count nt
+// and last node index nmax; returns the count and fills t[0..1], l[0..1].
+__device__ __forceinline__ int axis_tiles(int c, int w, int nt, int nmax, int* t, int* l) {
+  int k = 0;
+  const int hi = c / w;
+  if (c % w == 0 && hi - 1 >= 0) {
+    t[k] = hi - 1;
+    l[k] = w;
+    ++k;
+  }
+  if (hi < nt) {
+    t[k] = hi;
+    l[k] = c - hi * w;
+    ++k;
+  }
+  (void)nmax;
+  return k;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+    k_fixup3(Geo G, Tiles T, const double* __restrict__ side, const double2* __restrict__ F0,
+             const double* __restrict__ eps_dev, double2* __restrict__ out0,
+             double2* __restrict__ out1) {
+  constexpr int NO = ModeInfo<MODE>::NO;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= G.n_nodes) return;
+  const int x = (int)(i % G.nn[0]);
+  const long long r = i / G.nn[0];
+  const int y = (int)(r % G.nn[1]);
+  const int z = (int)(r / G.nn[1]);
+  const bool ringx = (x % TX == 0) || x == G.n[0];
+  const bool ringy = (y % TY == 0) || y == G.n[1];
+  const bool ringz = (z % KZ == 0) || z == G.n[2];
+  if (!(ringx || ringy || ringz)) return;
+  int txs[2], lxs[2], tys[2], lys[2], tzs[2], lzs[2];
+  const int nx = axis_tiles(x, TX, T.ntx, G.n[0], txs, lxs);
+  const int ny = axis_tiles(y, TY, T.nty, G.n[1], tys, lys);
+  const int nz = axis_tiles(z, KZ, T.ntz, G.n[2], tzs, lzs);
+  double acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+  for (int c = 0; c < nz; ++c)
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a) {
+        const long long tile = txs[a] + (long long)T.ntx * (tys[b] + (long long)T.nty * tzs[c]);
+        const long long n = lxs[a] + PX * lys[b];
+        const double* s = side + ((tile * (KZ + 1) + lzs[c]) * PN + n) * NO;
+#pragma unroll
+        for (int o = 0; o < NO; ++o) acc[o] += s[o];
+      }
+  if (MODE == MODE_FD) {
+    const double eps = *eps_dev;
+    const double ie = eps == 0.0 ? 0.0 : 1.0 / eps;
+    const double2 f0 = F0[i];
+    out0[i] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
+  } else {
+    if (out0) out0[i] = make_double2(acc[0], acc[1]);
+    if (NO == 4 && out1) out1[i] = make_double2(acc[2 % NO], acc[3 % NO]);
+  }
+}
+
+Tiles tiles_for(const Geo& G) {
+  Tiles T;
+  T.ntx = (G.n[0] + TX - 1) / TX;
+  T.nty = (G.n[1] + TY - 1) / TY;
+  T.ntz = (G.n[2] + KZ - 1) / KZ;
+  return T;
+}
+
+template <int MODE>
+int launch_mode(pf_problem* pb, const double* U, const double* Uprev, const double* v,
+                const double* F0, const double* eps_dev, double* out0, double* out1,
+                double* vjp_part, hipStream_t s) {
+  const Geo& G = pb->geo;
+  const Tiles T = tiles_for(G);
+  const unsigned nt = (unsigned)(T.ntx * T.nty * T.ntz);
+  auto d2 = [](const double* p) { return reinterpret_cast<const double2*>(p); };
+  hipLaunchKernelGGL((k_fused3<MODE>), dim3(nt), dim3(kThreads), 0, s, G, T, d2(U), d2(Uprev),
+                     d2(v), eps_dev, d2(F0), reinterpret_cast<double2*>(out0),
+                     reinterpret_cast<double2*>(out1), pb->side_buf, vjp_part);
+  PF_HIP_CHECK(hipGetLastError());
+  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
+  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb), dim3(256), 0, s, G, T, pb->side_buf, d2(F0),
+                     eps_dev, reinterpret_cast<double2*>(out0), reinterpret_cast<double2*>(out1));
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+}  // namespace
+
+long long fused3_side_len(const Geo& G) {
+  const Tiles T = tiles_for(G);
+  return (long long)T.ntx * T.nty * T.ntz * (KZ + 1) * PN * 4;
+}
+
+int fused3_tiles(const Geo& G) {
+  const Tiles T = tiles_for(G);
+  return T.ntx * T.nty * T.ntz;
+}
+
+int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
+                  const double* F0, const double* eps_dev, double* out0, double* out1,
+                  double* vjp_part, hipStream_t s) {
+  switch (mode) {
+    case MODE_RES:
+      return launch_mode<MODE_RES>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+    case MODE_FD:
+      return launch_mode<MODE_FD>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+    case MODE_JVP:
+      return launch_mode<MODE_JVP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+    default:
+      return launch_mode<MODE_VJP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+  }
+}
+
+}  // namespace pf

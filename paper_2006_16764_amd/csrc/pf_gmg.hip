@@ -12,9 +12,16 @@
 //           degree 16 on [lmin, 1.1 lmax] on the coarsest grid, with lmin,
 //           lmax the exact extreme eigenvalues of D^-1 A for constant
 //           coefficients (frequency corners of the Q1 symbol).
-// The operator is applied matrix-free: a Q1 element matrix on a box depends
-// only on which axes separate its two corners, so A x at a node is
-// sum over its cells e of c_e sum_b Ae[a ^ b] x_b with 2^dim table entries.
+//
+// Matrix-free node-centric operator: the Q1 element matrix entry between two
+// corners depends only on which axes separate them, so row i of A is a
+// 27-point (9-point) stencil whose weight for the neighbour at offset d is
+//   Ae[p(d)] * (sum of c_e over the cells shared by node i and node i + d),
+// p(d) = sum_k [d_k != 0] 2^k.  The shared-cell sums come from the 8 (4)
+// cells around the node by partial sums along each axis; cells outside the
+// mesh count as zero, which gives the natural-boundary rows.  The diagonal is
+// the d = 0 weight, so no diagonal array is stored.  Both blocks are processed
+// by the same thread and stored as interleaved (phi, u) pairs.
 #include <cmath>
 #include <vector>
 
@@ -25,45 +32,200 @@ namespace pf {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kCoarseMin = 4;
+constexpr int kCoarseDegree = 16;
+constexpr double kChebRatio = 4.0;
+constexpr double kChebSafety = 1.1;
+constexpr int kCoarseLdsNodes = 1024;  // coarsest grids up to this size are solved by one workgroup
 
-struct LevelGeo {
-  int dim;
+template <class T>
+struct V2;
+template <>
+struct V2<float> {
+  using type = float2;
+};
+template <>
+struct V2<double> {
+  using type = double2;
+};
+
+// Kernel-side description of one level (both blocks).
+struct LvK {
   int n[3];
   int nn[3];
   long long nnodes, ncells;
-  double Ae[8];  // element-matrix entry by corner-difference pattern
+  double Ae[2][8];  // element-matrix entry by corner-difference pattern, per block
 };
 
 template <class T>
 struct Level {
-  LevelGeo g;
+  LvK k;
   double h[3];
-  double lmin, lmax;
-  T* c;     // cell coefficients
-  T* dinv;  // inverse diagonal
-  T* xa;
-  T* xb;
-  T* b;
-  T* r;
-  T* d;
+  double lmin[2], lmax[2];
+  T* c;                          // phi-block cell coefficients
+  typename V2<T>::type* xa;      // iterates (phi, u)
+  typename V2<T>::type* xb;
+  typename V2<T>::type* b;       // right-hand side
+  typename V2<T>::type* r;       // residual
+  typename V2<T>::type* d;       // Chebyshev direction
 };
 
 template <class T>
 struct Hier {
   std::vector<Level<T>> lv;
-  double sm = 0.0, sk = 0.0;
   bool allocated = false;
+  double coarse_host[4 * kCoarseDegree];  // per-step (alpha, beta) of the coarsest solve
+  double* coarse_dev = nullptr;
 };
 
 struct PcState {
-  Hier<float> h32[2];
-  Hier<double> h64[2];
-  double* jacobi_dinv = nullptr;  // [2 * n_nodes] interleaved, FP64
-  double* coef0 = nullptr;        // FP64 cell coefficient of the phi block
+  Hier<float> h32;
+  Hier<double> h64;
+  double* coef0 = nullptr;  // FP64 cell coefficient of the phi block (level 0)
 };
 
-__host__ __device__ inline long long node_of(const LevelGeo& g, int i, int j, int k) {
+__host__ __device__ inline long long nidx(const LvK& g, int i, int j, int k) {
   return i + (long long)g.nn[0] * (j + (long long)g.nn[1] * k);
+}
+
+template <int DIM>
+__device__ __forceinline__ void node_ijk(const LvK& g, long long i, int& ix, int& iy, int& iz) {
+  ix = (int)(i % g.nn[0]);
+  const long long r = i / g.nn[0];
+  iy = DIM == 2 ? (int)r : (int)(r % g.nn[1]);
+  iz = DIM == 2 ? 0 : (int)(r / g.nn[1]);
+}
+
+// Stencil of node (ix, iy, iz) for both blocks: w[b][t] for the 3^DIM offsets t
+// (t = tx + 3 ty + 9 tz, offset t_k - 1).  Block 0 weights cells by c, block 1
+// by 1 (cells outside the mesh weigh 0).
+template <int DIM, class T>
+__device__ __forceinline__ void stencil(const LvK& g, const T* __restrict__ c, int ix, int iy,
+                                        int iz, T (&w0)[DIM == 3 ? 27 : 9],
+                                        T (&w1)[DIM == 3 ? 27 : 9]) {
+  constexpr int NZ = DIM == 3 ? 2 : 1;
+  T cc[NZ][2][2];  // [bz][by][bx]
+  bool ex[2], ey[2], ez[2];
+  ex[0] = ix - 1 >= 0;
+  ex[1] = ix < g.n[0];
+  ey[0] = iy - 1 >= 0;
+  ey[1] = iy < g.n[1];
+  ez[0] = DIM == 2 ? true : iz - 1 >= 0;
+  ez[1] = DIM == 2 ? true : iz < g.n[2];
+#pragma unroll
+  for (int bz = 0; bz < NZ; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const bool e = ex[bx] && ey[by] && (DIM == 2 || ez[bz]);
+        const int cx = ix - 1 + bx, cy = iy - 1 + by, cz = DIM == 3 ? iz - 1 + bz : 0;
+        T v = 0;
+        if (e) v = c ? c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * cz)] : (T)1;
+        cc[bz][by][bx] = v;
+      }
+  // partial sums over the shared cells: offset -1 -> side 0, +1 -> side 1, 0 -> both
+  T sx[3][NZ][2];
+#pragma unroll
+  for (int bz = 0; bz < NZ; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by) {
+      sx[0][bz][by] = cc[bz][by][0];
+      sx[2][bz][by] = cc[bz][by][1];
+      sx[1][bz][by] = cc[bz][by][0] + cc[bz][by][1];
+    }
+  T sxy[3][3][NZ];
+#pragma unroll
+  for (int tx = 0; tx < 3; ++tx)
+#pragma unroll
+    for (int bz = 0; bz < NZ; ++bz) {
+      sxy[tx][0][bz] = sx[tx][bz][0];
+      sxy[tx][2][bz] = sx[tx][bz][1];
+      sxy[tx][1][bz] = sx[tx][bz][0] + sx[tx][bz][1];
+    }
+  // block-1 counts factor per axis
+  T cxn[3], cyn[3], czn[3];
+  cxn[0] = ex[0] ? 1 : 0;
+  cxn[2] = ex[1] ? 1 : 0;
+  cxn[1] = cxn[0] + cxn[2];
+  cyn[0] = ey[0] ? 1 : 0;
+  cyn[2] = ey[1] ? 1 : 0;
+  cyn[1] = cyn[0] + cyn[2];
+  czn[0] = ez[0] ? 1 : 0;
+  czn[2] = ez[1] ? 1 : 0;
+  czn[1] = czn[0] + czn[2];
+#pragma unroll
+  for (int tz = 0; tz < (DIM == 3 ? 3 : 1); ++tz)
+#pragma unroll
+    for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        T s;
+        if (DIM == 3) {
+          const int a = tz == 0 ? 0 : (tz == 2 ? 1 : 2);
+          s = a == 0 ? sxy[tx][ty][0] : (a == 1 ? sxy[tx][ty][NZ - 1] : sxy[tx][ty][0] + sxy[tx][ty][NZ - 1]);
+        } else {
+          s = sxy[tx][ty][0];
+        }
+        const int p = (tx != 1 ? 1 : 0) + (ty != 1 ? 2 : 0) + (tz != 1 && DIM == 3 ? 4 : 0);
+        const int t = tx + 3 * ty + 9 * tz;
+        const T n1 = cxn[tx] * cyn[ty] * (DIM == 3 ? czn[tz] : (T)1);
+        w0[t] = (T)g.Ae[0][p] * s;
+        w1[t] = (T)g.Ae[1][p] * n1;
+      }
+}
+
+// (A x)_i for both blocks and the two diagonals.
+template <int DIM, class T>
+__device__ __forceinline__ void apply_A(const LvK& g, const T* __restrict__ c,
+                                        const typename V2<T>::type* __restrict__ x, int ix, int iy,
+                                        int iz, T& y0, T& y1, T& d0, T& d1) {
+  T w0[DIM == 3 ? 27 : 9], w1[DIM == 3 ? 27 : 9];
+  stencil<DIM, T>(g, c, ix, iy, iz, w0, w1);
+  y0 = 0;
+  y1 = 0;
+#pragma unroll
+  for (int tz = 0; tz < (DIM == 3 ? 3 : 1); ++tz) {
+    const int jz = DIM == 3 ? min(max(iz + tz - 1, 0), g.nn[2] - 1) : 0;
+#pragma unroll
+    for (int ty = 0; ty < 3; ++ty) {
+      const int jy = min(max(iy + ty - 1, 0), g.nn[1] - 1);
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        const int jx = min(max(ix + tx - 1, 0), g.nn[0] - 1);
+        const int t = tx + 3 * ty + 9 * tz;
+        const auto xv = x[nidx(g, jx, jy, jz)];
+        y0 += w0[t] * xv.x;
+        y1 += w1[t] * xv.y;
+      }
+    }
+  }
+  const int tc = DIM == 3 ? 13 : 4;
+  d0 = w0[tc];
+  d1 = w1[tc];
+}
+
+template <int DIM, class T>
+__device__ __forceinline__ void diag_only(const LvK& g, const T* __restrict__ c, int ix, int iy,
+                                          int iz, T& d0, T& d1) {
+  constexpr int NZ = DIM == 3 ? 2 : 1;
+  T s = 0, n = 0;
+#pragma unroll
+  for (int bz = 0; bz < NZ; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int cx = ix - 1 + bx, cy = iy - 1 + by, cz = DIM == 3 ? iz - 1 + bz : 0;
+        const bool e = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] &&
+                       (DIM == 2 || (cz >= 0 && cz < g.n[2]));
+        if (e) {
+          s += c ? c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * cz)] : (T)1;
+          n += (T)1;
+        }
+      }
+  d0 = (T)g.Ae[0][0] * s;
+  d1 = (T)g.Ae[1][0] * n;
 }
 
 // ----------------------------------------------------------------- kernels
@@ -90,7 +252,6 @@ __global__ void __launch_bounds__(kT)
 #pragma unroll
       for (int gx = 0; gx < 3; ++gx) {
         double g[3] = {0.0, 0.0, 0.0};
-        // gradient of the multilinear interpolant at the Gauss point
 #pragma unroll
         for (int a = 0; a < (1 << DIM); ++a) {
           const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
@@ -105,7 +266,7 @@ __global__ void __launch_bounds__(kT)
           if (DIM == 3) g[2] += p[a] * bx * by * dzz;
         }
         Aniso<DIM> A;
-        A.eval(g, G.eps4, G.delta2);
+        A.flux(g, G);
         const double w = Q1::w(gx) * Q1::w(gy) * (DIM == 3 ? Q1::w(gz) : 1.0);
         acc += w * A.a * A.a;
         wsum += w;
@@ -121,15 +282,9 @@ __global__ void k_convert(const double* __restrict__ x, T* __restrict__ y, long 
   if (i < n) y[i] = (T)x[i];
 }
 
-template <class T>
-__global__ void k_fill(T* __restrict__ y, T v, long long n) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i < n) y[i] = v;
-}
-
 // coarse cell = mean of its 2^dim children
 template <int DIM, class T>
-__global__ void k_coarsen(LevelGeo fg, LevelGeo cg, const T* __restrict__ cf, T* __restrict__ cc) {
+__global__ void k_coarsen(LvK fg, LvK cg, const T* __restrict__ cf, T* __restrict__ cc) {
   const long long E = (long long)blockIdx.x * kT + threadIdx.x;
   if (E >= cg.ncells) return;
   const int EX = (int)(E % cg.n[0]);
@@ -147,117 +302,89 @@ __global__ void k_coarsen(LevelGeo fg, LevelGeo cg, const T* __restrict__ cf, T*
   cc[E] = acc * (T)(DIM == 3 ? 0.125 : 0.25);
 }
 
-// y_i = (A x)_i; optionally r_i = b_i - (A x)_i.  Deterministic fixed order.
-template <int DIM, class T>
-__device__ __forceinline__ T apply_A(const LevelGeo& g, const T* __restrict__ c,
-                                     const T* __restrict__ x, int ix, int iy, int iz) {
-  T acc = 0;
-#pragma unroll
-  for (int bz = 0; bz < (DIM == 3 ? 2 : 1); ++bz) {
-    const int ez = DIM == 3 ? iz - 1 + bz : 0;
-    if (DIM == 3 && (ez < 0 || ez >= g.n[2])) continue;
-#pragma unroll
-    for (int by = 0; by < 2; ++by) {
-      const int ey = iy - 1 + by;
-      if (ey < 0 || ey >= g.n[1]) continue;
-#pragma unroll
-      for (int bx = 0; bx < 2; ++bx) {
-        const int ex = ix - 1 + bx;
-        if (ex < 0 || ex >= g.n[0]) continue;
-        const T ce = c ? c[ex + (long long)g.n[0] * (ey + (long long)g.n[1] * ez)] : (T)1;
-        const int a = (1 - bx) + 2 * (1 - by) + (DIM == 3 ? 4 * (1 - bz) : 0);
-        T s = 0;
-#pragma unroll
-        for (int b = 0; b < (1 << DIM); ++b) {
-          const T xb = x[node_of(g, ex + (b & 1), ey + ((b >> 1) & 1), ez + (DIM == 3 ? ((b >> 2) & 1) : 0))];
-          s += (T)g.Ae[a ^ b] * xb;
-        }
-        acc += ce * s;
-      }
-    }
-  }
-  return acc;
-}
-
-template <int DIM>
-__device__ __forceinline__ void node_ijk(const LevelGeo& g, long long i, int& ix, int& iy, int& iz) {
-  ix = (int)(i % g.nn[0]);
-  const long long r = i / g.nn[0];
-  iy = DIM == 2 ? (int)r : (int)(r % g.nn[1]);
-  iz = DIM == 2 ? 0 : (int)(r / g.nn[1]);
-}
-
-template <int DIM, class T>
+// One Jacobi-Chebyshev step for both blocks:
+//   d = alpha d + beta D^-1 (b - A x_in),  x_out = x_in + d.
+// IN: 0 zero start (x_in = 0, b from the level array); 1 zero start with b
+// read from the FP64 interleaved r64 and stored into b; 2 general step.
+// OUT: 0 writes x_out; 1 writes the FP64 interleaved z64 (last step).
+template <int DIM, class T, int IN, int OUT>
 __global__ void __launch_bounds__(kT)
-    k_diag(LevelGeo g, const T* __restrict__ c, T* __restrict__ dinv) {
+    k_smooth(LvK g, const T* __restrict__ c, typename V2<T>::type* __restrict__ b,
+             const typename V2<T>::type* __restrict__ x_in, typename V2<T>::type* __restrict__ x_out,
+             typename V2<T>::type* __restrict__ d, T al0, T al1, T be0, T be1,
+             const double2* __restrict__ r64, double2* __restrict__ z64) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= g.nnodes) return;
   int ix, iy, iz;
   node_ijk<DIM>(g, i, ix, iy, iz);
-  T acc = 0;
-#pragma unroll
-  for (int bz = 0; bz < (DIM == 3 ? 2 : 1); ++bz) {
-    const int ez = DIM == 3 ? iz - 1 + bz : 0;
-    if (DIM == 3 && (ez < 0 || ez >= g.n[2])) continue;
-#pragma unroll
-    for (int by = 0; by < 2; ++by) {
-      const int ey = iy - 1 + by;
-      if (ey < 0 || ey >= g.n[1]) continue;
-#pragma unroll
-      for (int bx = 0; bx < 2; ++bx) {
-        const int ex = ix - 1 + bx;
-        if (ex < 0 || ex >= g.n[0]) continue;
-        acc += c ? c[ex + (long long)g.n[0] * (ey + (long long)g.n[1] * ez)] : (T)1;
-      }
-    }
+  typename V2<T>::type bb;
+  if (IN == 1) {
+    const double2 rv = r64[i];
+    bb.x = (T)rv.x;
+    bb.y = (T)rv.y;
+    b[i] = bb;
+  } else {
+    bb = b[i];
   }
-  dinv[i] = (T)1 / (acc * (T)g.Ae[0]);
-}
-
-// One Jacobi-Chebyshev step.  zero_start: x = d = beta * dinv * b (x_in = 0).
-// Otherwise d = alpha d + beta dinv (b - A x_in), x_out = x_in + d.
-template <int DIM, class T>
-__global__ void __launch_bounds__(kT)
-    k_cheb(LevelGeo g, const T* __restrict__ c, const T* __restrict__ dinv,
-           const T* __restrict__ b, const T* __restrict__ x_in, T* __restrict__ x_out,
-           T* __restrict__ d, T alpha, T beta, int zero_start) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= g.nnodes) return;
-  if (zero_start) {
-    const T v = beta * dinv[i] * b[i];
-    d[i] = v;
-    x_out[i] = v;
-    return;
+  T r0, r1, dg0, dg1, xi0 = 0, xi1 = 0, dn0, dn1;
+  if (IN == 2) {
+    T y0, y1;
+    apply_A<DIM, T>(g, c, x_in, ix, iy, iz, y0, y1, dg0, dg1);
+    r0 = bb.x - y0;
+    r1 = bb.y - y1;
+    const auto xv = x_in[i];
+    xi0 = xv.x;
+    xi1 = xv.y;
+    const auto dv = d[i];
+    dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
+    dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
+  } else {
+    diag_only<DIM, T>(g, c, ix, iy, iz, dg0, dg1);
+    dn0 = be0 * bb.x / dg0;
+    dn1 = be1 * bb.y / dg1;
   }
-  int ix, iy, iz;
-  node_ijk<DIM>(g, i, ix, iy, iz);
-  const T r = b[i] - apply_A<DIM, T>(g, c, x_in, ix, iy, iz);
-  const T dn = (alpha == (T)0 ? (T)0 : alpha * d[i]) + beta * dinv[i] * r;
-  d[i] = dn;
-  x_out[i] = x_in[i] + dn;
+  typename V2<T>::type dn;
+  dn.x = dn0;
+  dn.y = dn1;
+  if (OUT == 1) {
+    z64[i] = make_double2((double)(xi0 + dn0), (double)(xi1 + dn1));
+  } else {
+    d[i] = dn;
+    typename V2<T>::type xo;
+    xo.x = xi0 + dn0;
+    xo.y = xi1 + dn1;
+    x_out[i] = xo;
+  }
 }
 
 template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
-    k_resid(LevelGeo g, const T* __restrict__ c, const T* __restrict__ b,
-            const T* __restrict__ x, T* __restrict__ r) {
+    k_resid(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
+            const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ r) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= g.nnodes) return;
   int ix, iy, iz;
   node_ijk<DIM>(g, i, ix, iy, iz);
-  r[i] = b[i] - apply_A<DIM, T>(g, c, x, ix, iy, iz);
+  T y0, y1, d0, d1;
+  apply_A<DIM, T>(g, c, x, ix, iy, iz, y0, y1, d0, d1);
+  const auto bv = b[i];
+  typename V2<T>::type o;
+  o.x = bv.x - y0;
+  o.y = bv.y - y1;
+  r[i] = o;
 }
 
 // b_c[I] = sum_i P[i, I] r_f[i]: fine neighbours 2I-1, 2I, 2I+1 per axis with
 // weights 1/2, 1, 1/2.
 template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
-    k_restrict(LevelGeo fg, LevelGeo cg, const T* __restrict__ rf, T* __restrict__ bc) {
+    k_restrict(LvK fg, LvK cg, const typename V2<T>::type* __restrict__ rf,
+               typename V2<T>::type* __restrict__ bc) {
   const long long I = (long long)blockIdx.x * kT + threadIdx.x;
   if (I >= cg.nnodes) return;
   int cx, cy, cz;
   node_ijk<DIM>(cg, I, cx, cy, cz);
-  T acc = 0;
+  T a0 = 0, a1 = 0;
 #pragma unroll
   for (int dz = -1; dz <= (DIM == 3 ? 1 : -1); ++dz) {
     const int fz = DIM == 3 ? 2 * cz + dz : 0;
@@ -272,73 +399,156 @@ __global__ void __launch_bounds__(kT)
       for (int dx = -1; dx <= 1; ++dx) {
         const int fx = 2 * cx + dx;
         if (fx < 0 || fx >= fg.nn[0]) continue;
-        const T wx = dx == 0 ? (T)1 : (T)0.5;
-        acc += (wx * wy * wz) * rf[node_of(fg, fx, fy, fz)];
+        const T w = (dx == 0 ? (T)1 : (T)0.5) * wy * wz;
+        const auto v = rf[nidx(fg, fx, fy, fz)];
+        a0 += w * v.x;
+        a1 += w * v.y;
       }
     }
   }
-  bc[I] = acc;
+  typename V2<T>::type o;
+  o.x = a0;
+  o.y = a1;
+  bc[I] = o;
 }
 
 // x_f[i] += sum_I P[i, I] e_c[I]
 template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
-    k_prolong_add(LevelGeo fg, LevelGeo cg, const T* __restrict__ ec, T* __restrict__ xf) {
+    k_prolong_add(LvK fg, LvK cg, const typename V2<T>::type* __restrict__ ec,
+                  typename V2<T>::type* __restrict__ xf) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= fg.nnodes) return;
   int fx, fy, fz;
   node_ijk<DIM>(fg, i, fx, fy, fz);
-  const int x0 = fx >> 1, x1 = (fx + 1) >> 1;
-  const int y0 = fy >> 1, y1 = (fy + 1) >> 1;
-  const int z0 = DIM == 3 ? fz >> 1 : 0, z1 = DIM == 3 ? (fz + 1) >> 1 : 0;
-  const T wx = (fx & 1) ? (T)0.5 : (T)1;
-  const T wy = (fy & 1) ? (T)0.5 : (T)1;
-  const T wz = (DIM == 3 && (fz & 1)) ? (T)0.5 : (T)1;
-  T acc = wx * wy * wz * ec[node_of(cg, x0, y0, z0)];
-  if (fx & 1) acc += wx * wy * wz * ec[node_of(cg, x1, y0, z0)];
-  if (fy & 1) acc += wx * wy * wz * ec[node_of(cg, x0, y1, z0)];
-  if ((fx & 1) && (fy & 1)) acc += wx * wy * wz * ec[node_of(cg, x1, y1, z0)];
-  if (DIM == 3 && (fz & 1)) {
-    acc += wx * wy * wz * ec[node_of(cg, x0, y0, z1)];
-    if (fx & 1) acc += wx * wy * wz * ec[node_of(cg, x1, y0, z1)];
-    if (fy & 1) acc += wx * wy * wz * ec[node_of(cg, x0, y1, z1)];
-    if ((fx & 1) && (fy & 1)) acc += wx * wy * wz * ec[node_of(cg, x1, y1, z1)];
+  const int xs[2] = {fx >> 1, (fx + 1) >> 1};
+  const int ys[2] = {fy >> 1, (fy + 1) >> 1};
+  const int zs[2] = {DIM == 3 ? fz >> 1 : 0, DIM == 3 ? (fz + 1) >> 1 : 0};
+  const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (DIM == 3 && (fz & 1)) ? 2 : 1;
+  const T w = ((fx & 1) ? (T)0.5 : (T)1) * ((fy & 1) ? (T)0.5 : (T)1) *
+              ((DIM == 3 && (fz & 1)) ? (T)0.5 : (T)1);
+  T a0 = 0, a1 = 0;
+  for (int kz = 0; kz < nzs; ++kz)
+    for (int ky = 0; ky < nys; ++ky)
+      for (int kx = 0; kx < nxs; ++kx) {
+        const auto v = ec[nidx(cg, xs[kx], ys[ky], zs[kz])];
+        a0 += v.x;
+        a1 += v.y;
+      }
+  auto x = xf[i];
+  x.x += w * a0;
+  x.y += w * a1;
+  xf[i] = x;
+}
+
+// Coarsest level: COARSE_DEGREE Chebyshev steps for both blocks by one
+// workgroup, iterates in LDS.  al/be: per-step coefficients, [step][block].
+template <int DIM, class T>
+__global__ void __launch_bounds__(1024)
+    k_coarse(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
+             typename V2<T>::type* __restrict__ x_res, const double* __restrict__ coef) {
+  using T2 = typename V2<T>::type;
+  __shared__ T2 xs[2][kCoarseLdsNodes];
+  __shared__ T2 ds[kCoarseLdsNodes];
+  const int n = (int)g.nnodes;
+  for (int k = 0; k < kCoarseDegree; ++k) {
+    const int src = k & 1, dst = src ^ 1;
+    const T al0 = (T)coef[4 * k + 0], al1 = (T)coef[4 * k + 1];
+    const T be0 = (T)coef[4 * k + 2], be1 = (T)coef[4 * k + 3];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      int ix, iy, iz;
+      node_ijk<DIM>(g, i, ix, iy, iz);
+      const T2 bb = b[i];
+      T dn0, dn1, x0 = 0, x1 = 0;
+      if (k == 0) {
+        T dg0, dg1;
+        diag_only<DIM, T>(g, c, ix, iy, iz, dg0, dg1);
+        dn0 = be0 * bb.x / dg0;
+        dn1 = be1 * bb.y / dg1;
+      } else {
+        T w0[DIM == 3 ? 27 : 9], w1[DIM == 3 ? 27 : 9];
+        stencil<DIM, T>(g, c, ix, iy, iz, w0, w1);
+        T y0 = 0, y1 = 0;
+#pragma unroll
+        for (int tz = 0; tz < (DIM == 3 ? 3 : 1); ++tz) {
+          const int jz = DIM == 3 ? min(max(iz + tz - 1, 0), g.nn[2] - 1) : 0;
+#pragma unroll
+          for (int ty = 0; ty < 3; ++ty) {
+            const int jy = min(max(iy + ty - 1, 0), g.nn[1] - 1);
+#pragma unroll
+            for (int tx = 0; tx < 3; ++tx) {
+              const int jx = min(max(ix + tx - 1, 0), g.nn[0] - 1);
+              const int t = tx + 3 * ty + 9 * tz;
+              const T2 xv = xs[src][(int)nidx(g, jx, jy, jz)];
+              y0 += w0[t] * xv.x;
+              y1 += w1[t] * xv.y;
+            }
+          }
+        }
+        const int tc = DIM == 3 ? 13 : 4;
+        const T2 xv = xs[src][i];
+        x0 = xv.x;
+        x1 = xv.y;
+        const T2 dv = ds[i];
+        dn0 = al0 * dv.x + be0 * (bb.x - y0) / w0[tc];
+        dn1 = al1 * dv.y + be1 * (bb.y - y1) / w1[tc];
+      }
+      T2 dn, xo;
+      dn.x = dn0;
+      dn.y = dn1;
+      xo.x = x0 + dn0;
+      xo.y = x1 + dn1;
+      ds[i] = dn;
+      xs[dst][i] = xo;
+    }
+    __syncthreads();
   }
-  xf[i] += acc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x_res[i] = xs[kCoarseDegree & 1][i];
+}
+
+__global__ void k_jacobi(Geo G, const double* __restrict__ c, const double2* __restrict__ r,
+                         double2* __restrict__ z, double ae0, double ae1) {
+  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
+  if (i >= G.n_nodes) return;
+  LvK g{};
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = G.n[k];
+    g.nn[k] = G.nn[k];
+  }
+  g.Ae[0][0] = ae0;
+  g.Ae[1][0] = ae1;
+  int ix, iy, iz;
+  double d0, d1;
+  if (G.dim == 3) {
+    node_ijk<3>(g, i, ix, iy, iz);
+    diag_only<3, double>(g, c, ix, iy, iz, d0, d1);
+  } else {
+    node_ijk<2>(g, i, ix, iy, iz);
+    diag_only<2, double>(g, c, ix, iy, iz, d0, d1);
+  }
+  const double2 a = r[i];
+  z[i] = make_double2(a.x / d0, a.y / d1);
 }
 
 template <class T>
-__global__ void k_split(const double2* __restrict__ r, T* __restrict__ b0, T* __restrict__ b1,
+__global__ void k_split(const double2* __restrict__ r, typename V2<T>::type* __restrict__ b,
                         long long n) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   const double2 v = r[i];
-  b0[i] = (T)v.x;
-  b1[i] = (T)v.y;
+  typename V2<T>::type o;
+  o.x = (T)v.x;
+  o.y = (T)v.y;
+  b[i] = o;
 }
 
 template <class T>
-__global__ void k_merge(const T* __restrict__ x0, const T* __restrict__ x1, double2* __restrict__ z,
+__global__ void k_merge(const typename V2<T>::type* __restrict__ x, double2* __restrict__ z,
                         long long n) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
-  z[i] = make_double2((double)x0[i], (double)x1[i]);
-}
-
-__global__ void k_jacobi(const double2* __restrict__ r, const double2* __restrict__ dinv,
-                         double2* __restrict__ z, long long n) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  const double2 a = r[i], d = dinv[i];
-  z[i] = make_double2(a.x * d.x, a.y * d.y);
-}
-
-template <class T>
-__global__ void k_interleave_dinv(const T* __restrict__ d0, const T* __restrict__ d1,
-                                  double2* __restrict__ out, long long n) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  out[i] = make_double2((double)d0[i], (double)d1[i]);
+  const auto v = x[i];
+  z[i] = make_double2((double)v.x, (double)v.y);
 }
 
 __global__ void k_copy2(const double2* __restrict__ x, double2* __restrict__ y, long long n) {
@@ -405,33 +615,44 @@ void symbol_extremes(int dim, const double* h, double sm, double sk, double* lo,
   *hi = mx;
 }
 
-constexpr int kCoarseMin = 4;
-constexpr int kCoarseDegree = 16;
-constexpr double kChebRatio = 4.0;
-constexpr double kChebSafety = 1.1;
+// Chebyshev step coefficients (alpha_k, beta_k), k = 0 .. degree-1, for the
+// iteration d_k = alpha_k d_{k-1} + beta_k D^-1 r_k on [lo, hi].
+void cheb_coefs(double lo, double hi, int degree, double* al, double* be) {
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < degree; ++k) {
+    if (k == 0) {
+      al[k] = 0.0;
+      be[k] = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      al[k] = rn * rho;
+      be[k] = 2.0 * rn / delta;
+      rho = rn;
+    }
+  }
+}
 
 template <class T>
-int hier_alloc(pf_problem* pb, Hier<T>& H, bool with_coef) {
+int hier_alloc(pf_problem* pb, Hier<T>& H) {
   const Geo& G = pb->geo;
   int n[3] = {G.n[0], G.n[1], G.dim == 3 ? G.n[2] : 1};
   double h[3] = {G.h[0], G.h[1], G.h[2]};
   H.lv.clear();
   while (true) {
     Level<T> L{};
-    L.g.dim = G.dim;
     for (int k = 0; k < 3; ++k) {
-      L.g.n[k] = (k < G.dim) ? n[k] : 1;
-      L.g.nn[k] = (k < G.dim) ? n[k] + 1 : 1;
+      L.k.n[k] = (k < G.dim) ? n[k] : 1;
+      L.k.nn[k] = (k < G.dim) ? n[k] + 1 : 1;
       L.h[k] = h[k];
     }
-    L.g.nnodes = (long long)L.g.nn[0] * L.g.nn[1] * L.g.nn[2];
-    L.g.ncells = (long long)L.g.n[0] * L.g.n[1] * L.g.n[2];
-    const size_t nb = (size_t)L.g.nnodes * sizeof(T);
-    if (with_coef) {
-      if (hipMalloc(&L.c, (size_t)L.g.ncells * sizeof(T)) != hipSuccess) return PF_ERR_OOM;
-    }
-    T** bufs[] = {&L.dinv, &L.xa, &L.xb, &L.b, &L.r, &L.d};
-    for (T** p : bufs)
+    L.k.nnodes = (long long)L.k.nn[0] * L.k.nn[1] * L.k.nn[2];
+    L.k.ncells = (long long)L.k.n[0] * L.k.n[1] * L.k.n[2];
+    const size_t nb = (size_t)L.k.nnodes * sizeof(typename V2<T>::type);
+    if (hipMalloc(&L.c, (size_t)L.k.ncells * sizeof(T)) != hipSuccess) return PF_ERR_OOM;
+    typename V2<T>::type** bufs[] = {&L.xa, &L.xb, &L.b, &L.r, &L.d};
+    for (auto p : bufs)
       if (hipMalloc(p, nb) != hipSuccess) return PF_ERR_OOM;
     H.lv.push_back(L);
     bool even = true;
@@ -446,6 +667,7 @@ int hier_alloc(pf_problem* pb, Hier<T>& H, bool with_coef) {
       h[k] *= 2.0;
     }
   }
+  if (hipMalloc(&H.coarse_dev, sizeof(H.coarse_host)) != hipSuccess) return PF_ERR_OOM;
   H.allocated = true;
   return PF_OK;
 }
@@ -454,12 +676,17 @@ template <class T>
 hipError_t hier_free(Hier<T>& H) {
   hipError_t first = hipSuccess;
   for (auto& L : H.lv) {
-    T* bufs[] = {L.c, L.dinv, L.xa, L.xb, L.b, L.r, L.d};
-    for (T* p : bufs) {
+    void* bufs[] = {L.c, L.xa, L.xb, L.b, L.r, L.d};
+    for (void* p : bufs) {
       if (!p) continue;
       const hipError_t e = hipFree(p);
       if (first == hipSuccess) first = e;
     }
+  }
+  if (H.coarse_dev) {
+    const hipError_t e = hipFree(H.coarse_dev);
+    if (first == hipSuccess) first = e;
+    H.coarse_dev = nullptr;
   }
   H.lv.clear();
   H.allocated = false;
@@ -467,118 +694,144 @@ hipError_t hier_free(Hier<T>& H) {
 }
 
 template <int DIM, class T>
-int hier_setup(Hier<T>& H, const double* c0_dev, double sm, double sk, hipStream_t s) {
-  H.sm = sm;
-  H.sk = sk;
+int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) {
+  const double sm[2] = {1.0 / pb->params.dt, 1.0 / pb->params.dt};
+  const double sk[2] = {1.0, pb->params.D};
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level<T>& L = H.lv[l];
-    element_table(DIM, L.h, sm, sk, L.g.Ae);
-    symbol_extremes(DIM, L.h, sm, sk, &L.lmin, &L.lmax);
-    if (L.c) {
-      if (l == 0) {
-        hipLaunchKernelGGL((k_convert<T>), dim3(blocks(L.g.ncells)), dim3(kT), 0, s, c0_dev, L.c,
-                           L.g.ncells);
-      } else {
-        hipLaunchKernelGGL((k_coarsen<DIM, T>), dim3(blocks(L.g.ncells)), dim3(kT), 0, s,
-                           H.lv[l - 1].g, L.g, H.lv[l - 1].c, L.c);
-      }
+    for (int f = 0; f < 2; ++f) {
+      element_table(DIM, L.h, sm[f], sk[f], L.k.Ae[f]);
+      symbol_extremes(DIM, L.h, sm[f], sk[f], &L.lmin[f], &L.lmax[f]);
+    }
+    if (l == 0) {
+      hipLaunchKernelGGL((k_convert<T>), dim3(blocks(L.k.ncells)), dim3(kT), 0, s, c0_dev, L.c,
+                         L.k.ncells);
+    } else {
+      hipLaunchKernelGGL((k_coarsen<DIM, T>), dim3(blocks(L.k.ncells)), dim3(kT), 0, s,
+                         H.lv[l - 1].k, L.k, (const T*)H.lv[l - 1].c, L.c);
+    }
+    PF_HIP_CHECK(hipGetLastError());
+  }
+  // per-step coefficients of the coarsest solve, [step][alpha0, alpha1, beta0, beta1]
+  const Level<T>& C = H.lv.back();
+  for (int f = 0; f < 2; ++f) {
+    double a[kCoarseDegree], b[kCoarseDegree];
+    cheb_coefs(C.lmin[f], kChebSafety * C.lmax[f], kCoarseDegree, a, b);
+    for (int k = 0; k < kCoarseDegree; ++k) {
+      H.coarse_host[4 * k + f] = a[k];
+      H.coarse_host[4 * k + 2 + f] = b[k];
+    }
+  }
+  PF_HIP_CHECK(hipMemcpy(H.coarse_dev, H.coarse_host, sizeof(H.coarse_host), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+template <int DIM, class T, int IN, int OUT>
+int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::type* x_out,
+                const double* al, const double* be, int k, const double* r64, double* z64,
+                hipStream_t s) {
+  hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+                     (const T*)L.c, L.b, x_in, x_out, L.d, (T)al[2 * k], (T)al[2 * k + 1],
+                     (T)be[2 * k], (T)be[2 * k + 1], reinterpret_cast<const double2*>(r64),
+                     reinterpret_cast<double2*>(z64));
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+// coefficients of the level's degree-2 smoother, [k][block]
+template <class T>
+void smoother_coefs(const Level<T>& L, double* al, double* be) {
+  for (int f = 0; f < 2; ++f) {
+    const double hi = kChebSafety * L.lmax[f];
+    double lo = L.lmax[f] / kChebRatio;
+    if (L.lmin[f] > lo) lo = L.lmin[f];
+    double a[2], b[2];
+    cheb_coefs(lo, hi, 2, a, b);
+    for (int k = 0; k < 2; ++k) {
+      al[2 * k + f] = a[k];
+      be[2 * k + f] = b[k];
+    }
+  }
+}
+
+// V-cycle from level l on the right-hand side in lv[l].b (or r64 at level 0);
+// the result is left in lv[l].xb (or written to z64 at level 0).
+template <int DIM, class T>
+int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64, hipStream_t s) {
+  Level<T>& L = H.lv[l];
+  const bool top = l == 0;
+  if (l + 1 == H.lv.size()) {
+    // coarsest grid: Chebyshev of degree kCoarseDegree on [lmin, 1.1 lmax]
+    if (top) {
+      hipLaunchKernelGGL((k_split<T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s,
+                         reinterpret_cast<const double2*>(r64), L.b, L.k.nnodes);
       PF_HIP_CHECK(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_diag<DIM, T>), dim3(blocks(L.g.nnodes)), dim3(kT), 0, s, L.g,
-                       (const T*)L.c, L.dinv);
-    PF_HIP_CHECK(hipGetLastError());
-  }
-  return PF_OK;
-}
-
-// Run a Jacobi-Chebyshev iteration of the given degree on level L for A x = b,
-// starting from *x (nullptr = zero).  Returns the buffer holding the result.
-template <int DIM, class T>
-int chebyshev(Level<T>& L, T* x0, int degree, bool coarse, hipStream_t s, T** result) {
-  const double hi = kChebSafety * L.lmax;
-  double lo = coarse ? L.lmin : L.lmax / kChebRatio;
-  if (!coarse && L.lmin > lo) lo = L.lmin;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
-  const double sigma = theta / delta;
-  double rho = 1.0 / sigma;
-  T* cur = x0;
-  T* bufs[2] = {L.xa, L.xb};
-  int which = (x0 == L.xa) ? 1 : 0;
-  for (int k = 0; k < degree; ++k) {
-    T alpha, beta;
-    if (k == 0) {
-      alpha = 0;
-      beta = (T)(1.0 / theta);
+    if (L.k.nnodes <= kCoarseLdsNodes) {
+      hipLaunchKernelGGL((k_coarse<DIM, T>), dim3(1), dim3(1024), 0, s, L.k, (const T*)L.c,
+                         (const typename V2<T>::type*)L.b, L.xb, (const double*)H.coarse_dev);
+      PF_HIP_CHECK(hipGetLastError());
     } else {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      alpha = (T)(rn * rho);
-      beta = (T)(2.0 * rn / delta);
-      rho = rn;
+      const double* co = H.coarse_host;
+      double al[2 * kCoarseDegree], be[2 * kCoarseDegree];
+      for (int k = 0; k < kCoarseDegree; ++k) {
+        al[2 * k] = co[4 * k];
+        al[2 * k + 1] = co[4 * k + 1];
+        be[2 * k] = co[4 * k + 2];
+        be[2 * k + 1] = co[4 * k + 3];
+      }
+      // ping-pong ending in xb (kCoarseDegree is even)
+      PF_TRY((smooth_step<DIM, T, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
+      for (int k = 1; k < kCoarseDegree; ++k) {
+        auto* in = (k & 1) ? L.xa : L.xb;
+        auto* out = (k & 1) ? L.xb : L.xa;
+        PF_TRY((smooth_step<DIM, T, 2, 0>(L, in, out, al, be, k, nullptr, nullptr, s)));
+      }
     }
-    T* out = bufs[which];
-    hipLaunchKernelGGL((k_cheb<DIM, T>), dim3(blocks(L.g.nnodes)), dim3(kT), 0, s, L.g,
-                       (const T*)L.c, (const T*)L.dinv, (const T*)L.b, (const T*)cur, out, L.d,
-                       alpha, beta, cur == nullptr ? 1 : 0);
-    PF_HIP_CHECK(hipGetLastError());
-    cur = out;
-    which ^= 1;
+    if (top) {
+      hipLaunchKernelGGL((k_merge<T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s,
+                         (const typename V2<T>::type*)L.xb, reinterpret_cast<double2*>(z64),
+                         L.k.nnodes);
+      PF_HIP_CHECK(hipGetLastError());
+    }
+    return PF_OK;
   }
-  *result = cur;
-  return PF_OK;
-}
-
-// V-cycle on levels l..end for the right-hand side already in lv[l].b.
-template <int DIM, class T>
-int vcycle(Hier<T>& H, size_t l, hipStream_t s, T** result) {
-  Level<T>& L = H.lv[l];
-  if (l + 1 == H.lv.size()) return chebyshev<DIM, T>(L, nullptr, kCoarseDegree, true, s, result);
-  T* x = nullptr;
-  PF_TRY((chebyshev<DIM, T>(L, nullptr, 2, false, s, &x)));
-  hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.g.nnodes)), dim3(kT), 0, s, L.g,
-                     (const T*)L.c, (const T*)L.b, (const T*)x, L.r);
+  double al[4], be[4];
+  smoother_coefs(L, al, be);
+  // pre-smoothing from zero: xa, then xb
+  if (top) PF_TRY((smooth_step<DIM, T, 1, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
+  else PF_TRY((smooth_step<DIM, T, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
+  PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
+  hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+                     (const T*)L.c, (const typename V2<T>::type*)L.b,
+                     (const typename V2<T>::type*)L.xb, L.r);
   PF_HIP_CHECK(hipGetLastError());
   Level<T>& C = H.lv[l + 1];
-  hipLaunchKernelGGL((k_restrict<DIM, T>), dim3(blocks(C.g.nnodes)), dim3(kT), 0, s, L.g, C.g,
-                     (const T*)L.r, C.b);
+  hipLaunchKernelGGL((k_restrict<DIM, T>), dim3(blocks(C.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
+                     (const typename V2<T>::type*)L.r, C.b);
   PF_HIP_CHECK(hipGetLastError());
-  T* ec = nullptr;
-  PF_TRY((vcycle<DIM, T>(H, l + 1, s, &ec)));
-  hipLaunchKernelGGL((k_prolong_add<DIM, T>), dim3(blocks(L.g.nnodes)), dim3(kT), 0, s, L.g, C.g,
-                     (const T*)ec, x);
+  PF_TRY((vcycle<DIM, T>(pb, H, l + 1, nullptr, nullptr, s)));
+  hipLaunchKernelGGL((k_prolong_add<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
+                     (const typename V2<T>::type*)C.xb, L.xb);
   PF_HIP_CHECK(hipGetLastError());
-  return chebyshev<DIM, T>(L, x, 2, false, s, result);
-}
-
-template <class T>
-int apply_gmg(pf_problem* pb, Hier<T>* H, const double* r, double* z, hipStream_t s) {
-  const long long n = pb->geo.n_nodes;
-  hipLaunchKernelGGL((k_split<T>), dim3(blocks(n)), dim3(kT), 0, s,
-                     reinterpret_cast<const double2*>(r), H[0].lv[0].b, H[1].lv[0].b, n);
-  PF_HIP_CHECK(hipGetLastError());
-  T* x[2];
-  for (int f = 0; f < 2; ++f) {
-    if (pb->geo.dim == 3) PF_TRY((vcycle<3, T>(H[f], 0, s, &x[f])));
-    else PF_TRY((vcycle<2, T>(H[f], 0, s, &x[f])));
-  }
-  hipLaunchKernelGGL((k_merge<T>), dim3(blocks(n)), dim3(kT), 0, s, (const T*)x[0], (const T*)x[1],
-                     reinterpret_cast<double2*>(z), n);
-  PF_HIP_CHECK(hipGetLastError());
+  // post-smoothing from the corrected iterate: xb -> xa -> xb (or z64)
+  PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xb, L.xa, al, be, 0, nullptr, nullptr, s)));
+  if (top) PF_TRY((smooth_step<DIM, T, 2, 1>(L, L.xa, nullptr, al, be, 1, nullptr, z64, s)));
+  else PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
   return PF_OK;
 }
 
 template <class T>
-int setup_gmg(pf_problem* pb, PcState* st, Hier<T>* H, hipStream_t s) {
-  for (int f = 0; f < 2; ++f)
-    if (!H[f].allocated) PF_TRY(hier_alloc<T>(pb, H[f], f == 0));
-  const double idt = 1.0 / pb->params.dt;
-  if (pb->geo.dim == 3) {
-    PF_TRY((hier_setup<3, T>(H[0], st->coef0, idt, 1.0, s)));
-    PF_TRY((hier_setup<3, T>(H[1], nullptr, idt, pb->params.D, s)));
-  } else {
-    PF_TRY((hier_setup<2, T>(H[0], st->coef0, idt, 1.0, s)));
-    PF_TRY((hier_setup<2, T>(H[1], nullptr, idt, pb->params.D, s)));
-  }
-  return PF_OK;
+int setup_gmg(pf_problem* pb, PcState* st, Hier<T>& H, hipStream_t s) {
+  if (!H.allocated) PF_TRY(hier_alloc<T>(pb, H));
+  if (pb->geo.dim == 3) return hier_setup<3, T>(pb, H, st->coef0, s);
+  return hier_setup<2, T>(pb, H, st->coef0, s);
+}
+
+template <class T>
+int apply_gmg(pf_problem* pb, Hier<T>& H, const double* r, double* z, hipStream_t s) {
+  if (pb->geo.dim == 3) return vcycle<3, T>(pb, H, 0, r, z, s);
+  return vcycle<2, T>(pb, H, 0, r, z, s);
 }
 
 }  // namespace
@@ -587,7 +840,6 @@ int pc_alloc(pf_problem* pb) {
   PcState* st = new PcState();
   pb->pc = st;
   if (hipMalloc(&st->coef0, (size_t)pb->geo.n_elems * sizeof(double)) != hipSuccess) return PF_ERR_OOM;
-  if (hipMalloc(&st->jacobi_dinv, (size_t)pb->n_dof * sizeof(double)) != hipSuccess) return PF_ERR_OOM;
   return PF_OK;
 }
 
@@ -598,12 +850,9 @@ hipError_t pc_free(pf_problem* pb) {
   auto keep = [&](hipError_t e) {
     if (first == hipSuccess) first = e;
   };
-  for (int f = 0; f < 2; ++f) {
-    keep(hier_free(st->h32[f]));
-    keep(hier_free(st->h64[f]));
-  }
+  keep(hier_free(st->h32));
+  keep(hier_free(st->h64));
   if (st->coef0) keep(hipFree(st->coef0));
-  if (st->jacobi_dinv) keep(hipFree(st->jacobi_dinv));
   delete st;
   pb->pc = nullptr;
   return first;
@@ -622,36 +871,31 @@ int pc_setup(pf_problem* pb, const double* U, int kind, int precision, hipStream
     hipLaunchKernelGGL(k_cell_coef<2>, dim3(blocks(G.n_elems)), dim3(kT), 0, s, G,
                        reinterpret_cast<const double2*>(U), st->coef0);
   PF_HIP_CHECK(hipGetLastError());
-  if (kind == PF_PC_JACOBI) {
-    // FP64 diagonals of both blocks on level 0 only
-    Hier<double>* H = st->h64;
-    PF_TRY(setup_gmg<double>(pb, st, H, s));
-    hipLaunchKernelGGL((k_interleave_dinv<double>), dim3(blocks(G.n_nodes)), dim3(kT), 0, s,
-                       (const double*)H[0].lv[0].dinv, (const double*)H[1].lv[0].dinv,
-                       reinterpret_cast<double2*>(st->jacobi_dinv), G.n_nodes);
-    PF_HIP_CHECK(hipGetLastError());
-    return PF_OK;
-  }
+  if (kind == PF_PC_JACOBI) return PF_OK;
   if (precision == PF_FP32) return setup_gmg<float>(pb, st, st->h32, s);
   return setup_gmg<double>(pb, st, st->h64, s);
 }
 
 int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s) {
   PcState* st = static_cast<PcState*>(pb->pc);
-  const long long n = pb->geo.n_nodes;
+  const Geo& G = pb->geo;
+  const long long n = G.n_nodes;
   switch (pb->pc_kind) {
     case PF_PC_NONE:
       hipLaunchKernelGGL(k_copy2, dim3(blocks(n)), dim3(kT), 0, s,
                          reinterpret_cast<const double2*>(r), reinterpret_cast<double2*>(z), n);
       PF_HIP_CHECK(hipGetLastError());
       return PF_OK;
-    case PF_PC_JACOBI:
-      hipLaunchKernelGGL(k_jacobi, dim3(blocks(n)), dim3(kT), 0, s,
-                         reinterpret_cast<const double2*>(r),
-                         reinterpret_cast<const double2*>(st->jacobi_dinv),
-                         reinterpret_cast<double2*>(z), n);
+    case PF_PC_JACOBI: {
+      double Ae0[8], Ae1[8];
+      element_table(G.dim, G.h, 1.0 / pb->params.dt, 1.0, Ae0);
+      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.D, Ae1);
+      hipLaunchKernelGGL(k_jacobi, dim3(blocks(n)), dim3(kT), 0, s, G, (const double*)st->coef0,
+                         reinterpret_cast<const double2*>(r), reinterpret_cast<double2*>(z),
+                         Ae0[0], Ae1[0]);
       PF_HIP_CHECK(hipGetLastError());
       return PF_OK;
+    }
     default:
       if (pb->pc_precision == PF_FP32) return apply_gmg<float>(pb, st->h32, r, z, s);
       return apply_gmg<double>(pb, st->h64, r, z, s);

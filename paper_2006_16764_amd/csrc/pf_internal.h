@@ -43,12 +43,20 @@ struct Geo {
   double ih[3];  // 1/h
   double jac;    // prod(h/2): Jacobian of the reference map
   double dt, idt, eps4, lam, D, delta2;
+  double a0, e4x4, e16;  // 1 - 3 eps4, 4 eps4, 16 eps4
 };
 
 Geo make_geo(const pf_params& p);
 
 // Element-loop modes of the residual kernel family.
 enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3 };
+
+// 3-D single-pass kernels (pf_fused3.hip).
+long long fused3_side_len(const Geo& G);
+int fused3_tiles(const Geo& G);
+int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
+                  const double* F0, const double* eps_dev, double* out0, double* out1,
+                  double* vjp_part, hipStream_t s);
 
 // Launch helpers (defined in pf_residual.hip).
 int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
@@ -107,6 +115,8 @@ struct pf_problem {
   double* elem_buf;      // element contributions (element pass)
   long long elem_buf_len;
   double* vjp_partials;  // 2 * n_elem_blocks
+  double* side_buf;      // 3-D: partial node sums on tile boundaries
+  long long side_len;
   int n_elem_blocks;
   double* eps_dev;       // FD epsilon (device scalar)
   double* tmp_vec[6];    // work vectors of n_dof doubles (kNumTmp)

@@ -39,7 +39,6 @@ __global__ void __launch_bounds__(kElemBlock)
            const double2* __restrict__ V, const double* __restrict__ eps_dev,
            double* __restrict__ E, double* __restrict__ vjp_part) {
   constexpr int NA = 1 << DIM;
-  constexpr int NF = (MODE == MODE_RES || MODE == MODE_FD) ? 4 : 5;
   constexpr int NO = (MODE == MODE_VJP) ? 4 : 2;
   const long long e = (long long)blockIdx.x * kElemBlock + threadIdx.x;
   const bool active = e < G.n_elems;
@@ -47,45 +46,28 @@ __global__ void __launch_bounds__(kElemBlock)
   if (active) {
     long long node[NA];
     corner_nodes<DIM>(G, e, node);
-    double nod[NF][NA];
+    double u0[NA], u1[NA], p0[NA], p1[NA], v0[NA], v1[NA];
     double eps = 0.0;
     if (MODE == MODE_FD) eps = *eps_dev;
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
       double2 u = U[node[a]];
       const double2 up = Up[node[a]];
+      double2 v = make_double2(0.0, 0.0);
+      if (MODE != MODE_RES) v = V[node[a]];
       if (MODE == MODE_FD) {
-        const double2 v = V[node[a]];
         u.x = fma(eps, v.x, u.x);
         u.y = fma(eps, v.y, u.y);
       }
-      nod[0][a] = u.x;
-      nod[1][a] = u.y;
-      nod[2][a] = u.x - up.x;
-      if (MODE == MODE_RES || MODE == MODE_FD) {
-        nod[3][a] = u.y - up.y;
-      } else {
-        const double2 v = V[node[a]];
-        nod[3][a] = v.x;
-        nod[4][a] = v.y;
-      }
+      u0[a] = u.x;
+      u1[a] = u.y;
+      p0[a] = up.x;
+      p1[a] = up.y;
+      v0[a] = v.x;
+      v1[a] = v.y;
     }
     double out[NO][NA];
-    if (MODE == MODE_RES || MODE == MODE_FD) {
-      PhysResidual<DIM> ph(G);
-      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
-      else element_eval2<NF, NO>(nod, out, G, ph);
-    } else if (MODE == MODE_JVP) {
-      PhysJvp<DIM> ph(G);
-      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
-      else element_eval2<NF, NO>(nod, out, G, ph);
-    } else {
-      PhysVjp<DIM> ph(G);
-      if constexpr (DIM == 3) element_eval3<NF, NO>(nod, out, G, ph);
-      else element_eval2<NF, NO>(nod, out, G, ph);
-      ge = ph.ge;
-      gl = ph.gl;
-    }
+    Element<DIM, MODE>::run(G, u0, u1, p0, p1, v0, v1, out, ge, gl);
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
@@ -215,11 +197,13 @@ int launch_residual_family(pf_problem* pb, int mode, const double* U, const doub
                            const double* v, const double* F0, const double* eps_dev,
                            double* out0, double* out1, double* vjp_part, hipStream_t s) {
   if (pb->geo.dim == 3)
-    return launch_dim<3>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+    return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
   return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
 }
 
+// Number of per-block partial sums the VJP writes (one per workgroup).
 int elem_blocks(const pf_problem* pb) {
+  if (pb->geo.dim == 3) return fused3_tiles(pb->geo);
   return (int)((pb->geo.n_elems + kElemBlock - 1) / kElemBlock);
 }
 
