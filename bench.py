@@ -46,22 +46,25 @@ def parse():
 
 
 def flops_per_element(dim):
-    """FP64 flops (add, mul = 1; FMA = 2) of the sum-factorised residual element.
+    """FP64 flops (add, mul = 1; FMA = 2) of the residual element as implemented.
 
-    Fields interpolated: phi, u, phi - phi^n, u - u^n (values), phi and u
-    (gradients); outputs F1, F2 with their value and flux parts; pointwise
-    physics 55 flops in 3-D (44 in 2-D) including one reciprocal.
-    3-D: corner differences 16 + z-derivatives 16 + 3 planes x (pz 48 +
-    contraction 64) + 9 rows x (qv 24 + qy 8 + qz 12 + contraction 56) +
-    27 points x (values 12 + gradients 16 + physics 55 + weight 1 +
-    contraction 34) = 4454.
-    2-D: corner differences 8 + 3 rows x (qv 24 + qy 8 + contraction 40) +
-    9 points x (values 12 + gradients 10 + physics 44 + weight 1 +
-    contraction 24) = 1043.
+    Linear part (u equation, latent heat) by exact tensor-product element
+    matrices; Gauss part for the phi equation with phi interpolated with its
+    gradient, u and (phi - phi^n)/dt as values, one output with value and flux
+    parts; pointwise physics 52 flops in 3-D (40 in 2-D) including a
+    reciprocal with two Newton steps and the a^2 accumulation for the
+    preconditioner coefficient.
+    3-D: corner differences and scalings 40 + linear part 264 + 3 planes x
+    (interpolation 44 + contraction 32) + 9 rows x (interpolation 28 +
+    weights 2 + contraction 28) + 27 points x (interpolation 17 + physics 52
+    + weights 3 + contraction 14) = 3376.
+    2-D: corner differences and scalings 20 + linear part 88 + 3 rows x
+    (interpolation 14 + contraction 20) + 9 points x (interpolation 12 +
+    physics 40 + weights 3 + contraction 10) = 795.
     """
     if dim == 3:
-        return 16 + 16 + 3 * (48 + 64) + 9 * (24 + 8 + 12 + 56) + 27 * (12 + 16 + 55 + 1 + 34)
-    return 8 + 3 * (24 + 8 + 40) + 9 * (12 + 10 + 44 + 1 + 24)
+        return 40 + 264 + 3 * (44 + 32) + 9 * (28 + 2 + 28) + 27 * (17 + 52 + 3 + 14)
+    return 20 + 88 + 3 * (14 + 20) + 9 * (12 + 40 + 3 + 10)
 
 
 FLOPS_PER_ELEM = {3: flops_per_element(3), 2: flops_per_element(2)}
@@ -205,7 +208,7 @@ def main():
         "config": {"workload": f"{w.name}: {w.dim}-D Q1 {w.n}^{w.dim}, {w.n_seeds} seeds R={w.radius}, "
                                f"eps4={w.eps4:.5f}, u0={w.u0}, lambda={w.lam}, D={w.D}, dt={w.dt}",
                    "unknowns": n, "jv_applications": jv_count, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "residual element pass (k_elem + node gather)",
+        "roofline": {"bound": "alu", "kernel": "residual (k_fused3 + k_fixup3, one pf_residual call)",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "hbm_gbs_algorithmic": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / 8000.0, 4)},

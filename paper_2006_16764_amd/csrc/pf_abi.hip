@@ -135,14 +135,22 @@ struct Op {
   const double* Uprev;
   const double* F0;  // F(U) for the FD product
   int kind;          // 0 = J (FD), 1 = J (analytic), 2 = J^T
+  const double* unorm2 = nullptr;  // |U|^2 on the device (FD), computed by prepare()
+  int prepare(hipStream_t s) {
+    if (kind != 0) return PF_OK;
+    double* d = pb->red_out + 203;
+    PF_TRY(blas_multidot(pb, U, pb->n_dof, 1, U, pb->n_dof, d, s));
+    unorm2 = d;
+    return PF_OK;
+  }
   int apply(const double* z, double* w, hipStream_t s) const {
     if (kind == 0) {
-      PF_TRY(blas_fd_eps(pb, U, z, pb->n_dof, pb->eps_dev, s));
+      PF_TRY(blas_fd_eps_cached(pb, unorm2, z, pb->n_dof, pb->eps_dev, s));
       return launch_residual_family(pb, MODE_FD, U, Uprev, z, F0, pb->eps_dev, w, nullptr, nullptr, s);
     }
     if (kind == 1)
       return launch_residual_family(pb, MODE_JVP, U, Uprev, z, nullptr, nullptr, w, nullptr, nullptr, s);
-    return launch_residual_family(pb, MODE_VJP, U, Uprev, z, nullptr, nullptr, w, nullptr,
+    return launch_residual_family(pb, MODE_VJPU, U, Uprev, z, nullptr, nullptr, w, nullptr,
                                   pb->vjp_partials, s);
   }
 };
@@ -186,16 +194,36 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
       double* w = V + (long long)(j + 1) * n;
       PF_TRY(pc_apply(pb, vj, zj, s));
       PF_TRY(op.apply(zj, w, s));
-      // classical Gram-Schmidt, twice
-      PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h1, s));
-      PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nullptr, 0, s));
-      PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h2, s));
-      PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
-      PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, h1, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
+      // classical Gram-Schmidt; the products with V_0..V_j and w itself (the
+      // last entry, |w|^2) come from one pass since w is stored as V_{j+1}
+      PF_TRY(blas_multidot(pb, V, n, j + 2, w, n, h1, s));
+      PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, h1, (j + 2) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
       PF_HIP_CHECK(hipStreamSynchronize(s));
-      const double* hp = pb->host_pinned;
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hp[i] + hp[64 + i];
-      const double hn = std::sqrt(hp[128]);
+      double* hp = pb->host_pinned;
+      double hsq = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        H[i * m + j] = hp[i];
+        hsq += hp[i] * hp[i];
+      }
+      const double wsq = hp[j + 1];
+      double hn;
+      if (wsq - hsq > 0.5 * wsq) {
+        // less than half the norm lost: one pass is orthogonal to working accuracy
+        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nw, 1, s));
+        PF_TRY(fetch(pb, nw, 1, s));
+        hn = std::sqrt(pb->host_pinned[0]);
+      } else {
+        // second pass (CGS2)
+        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nullptr, 0, s));
+        PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h2, s));
+        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
+        PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned + 64, h2, 65 * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+        PF_HIP_CHECK(hipStreamSynchronize(s));
+        for (int i = 0; i <= j; ++i) H[i * m + j] += hp[64 + i];
+        hn = std::sqrt(hp[128]);
+      }
       H[(j + 1) * m + j] = hn;
       if (!std::isfinite(hn)) {
         set_error("non-finite Arnoldi coefficient in FGMRES");
@@ -269,7 +297,9 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
   double* Ft = pb->tmp_vec[4];
   double* B = pb->tmp_vec[5];
   (void)rhs;
-  PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, nullptr, s));
+  double* coef = pc_coef_buffer(pb);
+  PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
+                                nullptr, s, coef));
   double f;
   PF_TRY(norm2(pb, F, &f, s));
   if (!std::isfinite(f)) {
@@ -293,9 +323,11 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
       }
       return PF_ERR_NOT_CONVERGED;
     }
-    PF_TRY(pc_setup(pb, U, o.pc, o.pc_precision, s));
+    // the cell coefficients of the preconditioner came with the residual at U
+    PF_TRY(pc_setup_prepared(pb, o.pc, o.pc_precision, s));
     PF_TRY(blas_axpby(-1.0, F, 0.0, F, B, n, s));
     Op op{pb, U, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
+    PF_TRY(op.prepare(s));
     int its = 0;
     int rc = fgmres(pb, op, B, dU, eta, o, &its, s);
     if (st) {
@@ -311,7 +343,8 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
     bool ok = false;
     for (int bt = 0; bt <= o.max_backtracks; ++bt) {
       PF_TRY(blas_axpby(1.0, U, lam, dU, Ut, n, s));
-      PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr, nullptr, s));
+      PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr,
+                                    nullptr, s, coef));
       PF_TRY(norm2(pb, Ft, &ft, s));
       if (std::isfinite(ft) && ft <= f) {
         ok = true;
@@ -633,6 +666,7 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
   if (kind == 0)
     PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, nullptr, s));
   Op op{pb, U, Uprev, F, kind};
+  PF_TRY(op.prepare(s));
   int its = 0;
   int rc = fgmres(pb, op, b, x, rtol, *opts, &its, s);
   if (stats) {

@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(256)
 }
 
 // eps = sqrt(2^-52) (1 + sqrt(uu)) / sqrt(vv), 0 when v = 0
-__global__ void k_fd_eps(const double* __restrict__ norms2, double* __restrict__ eps) {
-  const double nu = sqrt(norms2[0]), nv = sqrt(norms2[1]);
+__global__ void k_fd_eps(const double* __restrict__ uu, const double* __restrict__ vv,
+                         double* __restrict__ eps) {
+  const double nu = sqrt(uu[0]), nv = sqrt(vv[0]);
   eps[0] = (nv > 0.0) ? 1.4901161193847656e-08 * (1.0 + nu) / nv : 0.0;
 }
 
@@ -238,7 +239,16 @@ int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, d
   double* nrm = pb->red_out + 200;
   PF_TRY(blas_multidot(pb, U, n, 1, U, n, nrm, s));
   PF_TRY(blas_multidot(pb, v, n, 1, v, n, nrm + 1, s));
-  hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, nrm, eps_dev);
+  hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, nrm, nrm + 1, eps_dev);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+int blas_fd_eps_cached(pf_problem* pb, const double* unorm2_dev, const double* v, long long n,
+                       double* eps_dev, hipStream_t s) {
+  double* nv = pb->red_out + 201;
+  PF_TRY(blas_multidot(pb, v, n, 1, v, n, nv, s));
+  hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, unorm2_dev, nv, eps_dev);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

@@ -325,34 +325,11 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
 // J = a^2 g + a |g|^2 da/dg (gradient of a^2 |g|^2 / 2).
 template <int DIM>
 struct Aniso {
-  double q, S, iQ, a, da[3], J[3];
-  // full evaluation (a, da/dg and J)
-  __device__ __forceinline__ void eval(const double* g, const Geo& G) {
-    double g2[3];
-    q = 0.0;
-    S = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      g2[k] = g[k] * g[k];
-      q += g2[k];
-      S = fma(g2[k], g2[k], S);
-    }
-    iQ = rcp_nr(q + G.delta2);
-    const double iQ2 = iQ * iQ;
-    a = fma(G.e4x4 * S, iQ2, G.a0);
-    const double SQ = S * iQ;
-    const double c = G.e16 * iQ2;
-    const double a2 = a * a, aqc = a * q * c;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double t = g2[k] - SQ;
-      da[k] = c * g[k] * t;
-      J[k] = g[k] * fma(aqc, t, a2);
-    }
-  }
-  // a and J only: J_k = g_k (a^2 + a q 16 eps4 (g_k^2 - S/Q)/Q^2)
+  // primal quantities kept for the tangent: q = |g|^2, S = sum g^4, iQ = 1/Q,
+  // iQ2 = 1/Q^2, a, a^2, aqc = a q 16 eps4/Q^2, SQ = S/Q, g2_k = g_k^2 and
+  // t_k with J_k = g_k t_k, t_k = a^2 + aqc (g_k^2 - S/Q).
+  double q, S, iQ, iQ2, a, a2, aqc, SQ, g2[3], t[3], J[3];
   __device__ __forceinline__ void flux(const double* g, const Geo& G) {
-    double g2[3];
     q = 0.0;
     S = 0.0;
 #pragma unroll
@@ -362,34 +339,49 @@ struct Aniso {
       S = fma(g2[k], g2[k], S);
     }
     iQ = rcp_nr(q + G.delta2);
-    const double iQ2 = iQ * iQ;
+    iQ2 = iQ * iQ;
     a = fma(G.e4x4 * S, iQ2, G.a0);
-    const double SQ = S * iQ;
-    const double a2 = a * a, aqc = a * q * (G.e16 * iQ2);
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) J[k] = g[k] * fma(aqc, g2[k] - SQ, a2);
-  }
-  // H v with H the Hessian of a^2 |g|^2 / 2:
-  // H v = a^2 v + 2a (g (da.v) + da (g.v)) + q da (da.v) + a q 4 eps4 T v,
-  // T v = 12 g^2 v/Q^2 - 16 (g^3 (g.v) + g (g^3.v))/Q^3 - 4 S v/Q^3 + 24 S g (g.v)/Q^4.
-  __device__ __forceinline__ void hess(const double* g, const double* v, double e4x4,
-                                       double* Hv) const {
-    double gv = 0.0, dav = 0.0, g3v = 0.0;
+    SQ = S * iQ;
+    a2 = a * a;
+    aqc = a * q * (G.e16 * iQ2);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      gv += g[k] * v[k];
-      dav += da[k] * v[k];
-      g3v += g[k] * g[k] * g[k] * v[k];
+      t[k] = fma(aqc, g2[k] - SQ, a2);
+      J[k] = g[k] * t[k];
     }
-    const double iQ2 = iQ * iQ, iQ3 = iQ2 * iQ, iQ4 = iQ2 * iQ2;
-    const double a2 = a * a;
-    const double c4 = e4x4 * a * q;
+  }
+  // da/dg_k = 16 eps4 g_k (g_k^2 - S/Q)/Q^2 (after flux())
+  __device__ __forceinline__ double dadg(const double* g, int k, const Geo& G) const {
+    return G.e16 * iQ2 * g[k] * (g2[k] - SQ);
+  }
+  // Directional derivative along v (after flux()): Hv = (dJ/dg) v, the Hessian
+  // of a^2 |g|^2 / 2 times v (symmetric), and da = (da/dg) . v.  Forward-mode
+  // differentiation of flux():
+  //   dq = 2 g.v, dS = 4 sum g^3 v, d(1/Q) = -dq/Q^2, d(1/Q^2) = -2 dq/Q^3,
+  //   da = 4 eps4 (dS/Q^2 + S d(1/Q^2)), d(a^2) = 2 a da,
+  //   d(aqc) = 16 eps4 (da q/Q^2 + a dq/Q^2 + a q d(1/Q^2)),
+  //   d(S/Q) = dS/Q + S d(1/Q),
+  //   dt_k = d(a^2) + d(aqc) (g_k^2 - S/Q) + aqc (2 g_k v_k - d(S/Q)),
+  //   (Hv)_k = v_k t_k + g_k dt_k.
+  __device__ __forceinline__ void hvp(const double* g, const double* v, const Geo& G, double* Hv,
+                                      double& da) const {
+    double gv = 0.0, g3v = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double gk = g[k];
-      const double Tv = 12.0 * gk * gk * v[k] * iQ2 - 16.0 * (gk * gk * gk * gv + gk * g3v) * iQ3 -
-                        4.0 * S * v[k] * iQ3 + 24.0 * S * gk * gv * iQ4;
-      Hv[k] = a2 * v[k] + 2.0 * a * (gk * dav + da[k] * gv) + q * da[k] * dav + c4 * Tv;
+      gv = fma(g[k], v[k], gv);
+      g3v = fma(g2[k] * g[k], v[k], g3v);
+    }
+    const double dq = 2.0 * gv, dS = 4.0 * g3v;
+    const double diQ = -iQ2 * dq;
+    const double diQ2 = 2.0 * iQ * diQ;
+    da = G.e4x4 * fma(dS, iQ2, S * diQ2);
+    const double da2 = 2.0 * a * da;
+    const double daqc = G.e16 * fma(da * q, iQ2, a * fma(dq, iQ2, q * diQ2));
+    const double dSQ = fma(dS, iQ, S * diQ);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double dt = fma(daqc, g2[k] - SQ, fma(aqc, fma(2.0 * g[k], v[k], -dSQ), da2));
+      Hv[k] = fma(v[k], t[k], g[k] * dt);
     }
   }
 };
@@ -400,8 +392,10 @@ template <int DIM>
 struct PhysResidual {
   static constexpr int kGxUnroll = 1;
   const Geo& G;
-  __device__ PhysResidual(const Geo& g) : G(g) {}
-  __device__ __forceinline__ void weight(double) {}
+  double ca;  // sum of w_q a^2 over the element (preconditioner coefficient)
+  double a2;
+  __device__ PhysResidual(const Geo& g) : G(g), ca(0.0), a2(0.0) {}
+  __device__ __forceinline__ void weight(double wq) { ca = fma(wq, a2, ca); }
   // vv[1] holds (phi - phi^n)/dt
   __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
                                              const double* vv, double* s, double (*f)[3],
@@ -409,9 +403,10 @@ struct PhysResidual {
     const double phi = gv[0], u = vv[0], dphi_dt = vv[1];
     Aniso<DIM> A;
     A.flux(gg[0], G);
+    a2 = A.a * A.a;
     const double om = fma(-phi, phi, 1.0);
     const double R = om * fma(-G.lam * om, u, phi);  // phi - phi^3 - lambda (1-phi^2)^2 u
-    s[0] = fma(A.a * A.a, dphi_dt, -R);
+    s[0] = fma(a2, dphi_dt, -R);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? A.J[k] : 0.0;
   }
@@ -430,17 +425,15 @@ struct PhysJvp {
                                              double*) {
     const double phi = gv[0], tp = gv[1], u = vv[0], dphi = vv[1], tu = vv[2];
     Aniso<DIM> A;
-    A.eval(gg[0], G);
-    double dav = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) dav += A.da[k] * gg[1][k];
+    A.flux(gg[0], G);
+    double Hv[3] = {0.0, 0.0, 0.0};
+    double dav;
+    A.hvp(gg[0], gg[1], G, Hv, dav);
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;  // dR/dphi
     const double Ru = -G.lam * om * om;                              // dR/du
-    s[0] = (2.0 * A.a * dav * dphi + A.a * A.a * tp) * G.idt - (Rp * tp + Ru * tu);
-    double Hv[3] = {0.0, 0.0, 0.0};
-    A.hess(gg[0], gg[1], G.e4x4, Hv);
+    s[0] = (2.0 * A.a * dav * dphi + A.a2 * tp) * G.idt - (Rp * tp + Ru * tu);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hv[k] : 0.0;
   }
@@ -466,33 +459,61 @@ struct PhysVjp {
                                              double* p) {
     const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
     Aniso<DIM> A;
-    A.eval(gg[0], G);
+    A.flux(gg[0], G);
+    double Hw[3] = {0.0, 0.0, 0.0};
+    double daw;
+    A.hvp(gg[0], gg[1], G, Hw, daw);
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
-    const double a2 = A.a * A.a;
-    double Hw[3] = {0.0, 0.0, 0.0};
-    A.hess(gg[0], gg[1], G.e4x4, Hw);
     const double m = 2.0 * A.a * dphi * G.idt * w1;  // d(a^2 dphi/dt w1)/da
-    s[0] = w1 * (a2 * G.idt - Rp);
+    s[0] = w1 * (A.a2 * G.idt - Rp);
     p[0] = w1 * G.lam * om * om;
-    p[1] = -w1 * a2 * G.idt;
-    // parameter derivatives: da/deps4 = -3 + 4 S/Q^2, d(da)/deps4 = da/eps4
-    const double iQ2 = A.iQ * A.iQ;
-    const double ae = -3.0 + 4.0 * A.S * iQ2;
-    const double SQ = A.S * A.iQ;
+    p[1] = -w1 * A.a2 * G.idt;
+    // parameter derivatives: da/deps4 = -3 + 4 S/Q^2, d(da/dg)/deps4 = (da/dg)/eps4
+    const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
     double Je_w = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const double gk = gg[0][k];
-      const double dae = 16.0 * iQ2 * gk * (gk * gk - SQ);
-      const double Je = 2.0 * A.a * ae * gk + ae * A.q * A.da[k] + A.a * A.q * dae;
+      const double dae = 16.0 * A.iQ2 * gk * (A.g2[k] - A.SQ);
+      const double dak = G.eps4 * dae;
+      const double Je = 2.0 * A.a * ae * gk + ae * A.q * dak + A.a * A.q * dae;
       Je_w += Je * gg[1][k];
+      f[0][k] = Hw[k] + m * dak;
     }
+#pragma unroll
+    for (int k = DIM; k < 3; ++k) f[0][k] = 0.0;
     pe = m * ae + Je_w;
     pl = w1 * om * om * u;
+  }
+};
+
+// Adjoint of F1 restricted to (dF1/dU)^T w1: gradient fields {phi, w1}; value
+// fields {u, phi - phi^n}; outputs gU_phi (value + flux) and value-only gU_u.
+template <int DIM>
+struct PhysVjpU {
+  static constexpr int kGxUnroll = 3;
+  const Geo& G;
+  __device__ PhysVjpU(const Geo& g) : G(g) {}
+  __device__ __forceinline__ void weight(double) {}
+  __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
+                                             const double* vv, double* s, double (*f)[3],
+                                             double* p) {
+    const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
+    Aniso<DIM> A;
+    A.flux(gg[0], G);
+    double Hw[3] = {0.0, 0.0, 0.0};
+    double daw;
+    A.hvp(gg[0], gg[1], G, Hw, daw);
+    const double p2 = phi * phi;
+    const double om = 1.0 - p2;
+    const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
+    const double m = 2.0 * A.a * dphi * G.idt * w1;
+    s[0] = w1 * (A.a2 * G.idt - Rp);
+    p[0] = w1 * G.lam * om * om;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hw[k] + m * A.da[k] : 0.0;
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m, A.dadg(gg[0], k, G), Hw[k]) : 0.0;
   }
 };
 
@@ -501,6 +522,7 @@ struct PhysVjp {
 // (phi^n, u^n), v0/v1 = direction (JVP) or cotangent (VJP) parts.  For the FD
 // product the caller passes the perturbed state as u0/u1.  out[0..1][a] are the
 // two fields of the output vector; for the VJP out[2..3][a] those of gUprev.
+// ge, gl: VJP parameter sums; for the residual ge is the cell integral of a^2.
 template <int DIM, int MODE>
 struct Element {
   static constexpr int NA = 1 << DIM;
@@ -551,6 +573,7 @@ struct Element {
       quad<1, 2, 1, 0>(G, ngv, nvv, os, dummy, ph);
 #pragma unroll
       for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+      ge = ph.ca;  // cell integral of a^2 (the cell mean times the cell volume)
     } else if constexpr (MODE == MODE_JVP) {
       // d F2 = M (v_u - v_phi/2)/dt + D K v_u
       double y[NA];
@@ -571,6 +594,32 @@ struct Element {
       quad<2, 3, 1, 0>(G, ngv, nvv, os, dummy, ph);
 #pragma unroll
       for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+    } else if constexpr (MODE == MODE_VJPU) {
+      double ngv[2][NA], nvv[2][NA], os[1][NA], op[1][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        ngv[0][a] = u0[a];
+        ngv[1][a] = v0[a];
+        nvv[0][a] = u1[a];
+        nvv[1][a] = dphi[a];
+        os[0][a] = 0.0;
+        op[0][a] = 0.0;
+      }
+      PhysVjpU<DIM> ph(G);
+      quad<2, 2, 1, 1>(G, ngv, nvv, os, op, ph);
+      // F2 part: gU_phi -= M w2/(2dt), gU_u += M w2/dt + D K w2
+      double y[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        y[a] = G.idt * v1[a];
+        out[0][a] = os[0][a];
+        out[1][a] = op[0][a];
+      }
+      lin(G, y, 1.0, v1, G.D, out[1]);
+      double zero[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) zero[a] = 0.0;
+      lin(G, y, -0.5, zero, 0.0, out[0]);
     } else {
       // F2 part of the adjoint (M, K symmetric): gU_phi -= M w2/(2dt),
       // gU_u += M w2/dt + D K w2, gUprev_phi += M w2/(2dt), gUprev_u -= M w2/dt

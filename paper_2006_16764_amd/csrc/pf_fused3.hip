@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     k_fused3(Geo G, Tiles T, const double2* __restrict__ U, const double2* __restrict__ Up,
              const double2* __restrict__ V, const double* __restrict__ eps_dev,
              const double2* __restrict__ F0, double2* __restrict__ out0, double2* __restrict__ out1,
-             double* __restrict__ side, double* __restrict__ vjp_part) {
+             double* __restrict__ side, double* __restrict__ vjp_part, double* __restrict__ coef) {
   using MI = ModeInfo<MODE>;
   constexpr int NO = MI::NO;
   __shared__ double2 su[2][PN];
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
         u1[a] = u.y;
         p0[a] = up.x;
         p1[a] = up.y;
-        if (MODE == MODE_JVP || MODE == MODE_VJP) {
+        if (MODE == MODE_JVP || MODE == MODE_VJP || MODE == MODE_VJPU) {
           const double2 v = sv[slot][n];
           v0[a] = v.x;
           v1[a] = v.y;
@@ -167,8 +167,14 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
       }
       double eg = 0.0, lg = 0.0;
       Element<3, MODE>::run(G, u0, u1, p0, p1, v0, v1, out, eg, lg);
-      ge += eg;
-      gl += lg;
+      if (MODE == MODE_RES) {
+        // cell mean of a^2 for the preconditioner (weights sum to 8 jac)
+        if (coef) coef[(x0 + ei) + (long long)G.n[0] * ((y0 + ej) + (long long)G.n[1] * (z0 + kz))] =
+            eg / (8.0 * G.jac);
+      } else {
+        ge += eg;
+        gl += lg;
+      }
     } else {
 #pragma unroll
       for (int o = 0; o < NO; ++o)
@@ -301,14 +307,14 @@ Tiles tiles_for(const Geo& G) {
 template <int MODE>
 int launch_mode(pf_problem* pb, const double* U, const double* Uprev, const double* v,
                 const double* F0, const double* eps_dev, double* out0, double* out1,
-                double* vjp_part, hipStream_t s) {
+                double* vjp_part, double* coef, hipStream_t s) {
   const Geo& G = pb->geo;
   const Tiles T = tiles_for(G);
   const unsigned nt = (unsigned)(T.ntx * T.nty * T.ntz);
   auto d2 = [](const double* p) { return reinterpret_cast<const double2*>(p); };
   hipLaunchKernelGGL((k_fused3<MODE>), dim3(nt), dim3(kThreads), 0, s, G, T, d2(U), d2(Uprev),
                      d2(v), eps_dev, d2(F0), reinterpret_cast<double2*>(out0),
-                     reinterpret_cast<double2*>(out1), pb->side_buf, vjp_part);
+                     reinterpret_cast<double2*>(out1), pb->side_buf, vjp_part, coef);
   PF_HIP_CHECK(hipGetLastError());
   const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
   hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb), dim3(256), 0, s, G, T, pb->side_buf, d2(F0),
@@ -331,16 +337,18 @@ int fused3_tiles(const Geo& G) {
 
 int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
                   const double* F0, const double* eps_dev, double* out0, double* out1,
-                  double* vjp_part, hipStream_t s) {
+                  double* vjp_part, double* coef, hipStream_t s) {
   switch (mode) {
     case MODE_RES:
-      return launch_mode<MODE_RES>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+      return launch_mode<MODE_RES>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
     case MODE_FD:
-      return launch_mode<MODE_FD>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+      return launch_mode<MODE_FD>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     case MODE_JVP:
-      return launch_mode<MODE_JVP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+      return launch_mode<MODE_JVP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+    case MODE_VJPU:
+      return launch_mode<MODE_VJPU>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     default:
-      return launch_mode<MODE_VJP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+      return launch_mode<MODE_VJP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
   }
 }
 

@@ -99,31 +99,14 @@ __device__ __forceinline__ void node_ijk(const LvK& g, long long i, int& ix, int
 // Stencil of node (ix, iy, iz) for both blocks: w[b][t] for the 3^DIM offsets t
 // (t = tx + 3 ty + 9 tz, offset t_k - 1).  Block 0 weights cells by c, block 1
 // by 1 (cells outside the mesh weigh 0).
+// Weights from the block-0 cell coefficients around the node (cc, zero for
+// cells outside the mesh) and the per-axis existence flags of those cells.
 template <int DIM, class T>
-__device__ __forceinline__ void stencil(const LvK& g, const T* __restrict__ c, int ix, int iy,
-                                        int iz, T (&w0)[DIM == 3 ? 27 : 9],
-                                        T (&w1)[DIM == 3 ? 27 : 9]) {
+__device__ __forceinline__ void stencil_weights(const LvK& g, const T (&cc)[DIM == 3 ? 2 : 1][2][2],
+                                                const bool (&ex)[2], const bool (&ey)[2],
+                                                const bool (&ez)[2], T (&w0)[DIM == 3 ? 27 : 9],
+                                                T (&w1)[DIM == 3 ? 27 : 9]) {
   constexpr int NZ = DIM == 3 ? 2 : 1;
-  T cc[NZ][2][2];  // [bz][by][bx]
-  bool ex[2], ey[2], ez[2];
-  ex[0] = ix - 1 >= 0;
-  ex[1] = ix < g.n[0];
-  ey[0] = iy - 1 >= 0;
-  ey[1] = iy < g.n[1];
-  ez[0] = DIM == 2 ? true : iz - 1 >= 0;
-  ez[1] = DIM == 2 ? true : iz < g.n[2];
-#pragma unroll
-  for (int bz = 0; bz < NZ; ++bz)
-#pragma unroll
-    for (int by = 0; by < 2; ++by)
-#pragma unroll
-      for (int bx = 0; bx < 2; ++bx) {
-        const bool e = ex[bx] && ey[by] && (DIM == 2 || ez[bz]);
-        const int cx = ix - 1 + bx, cy = iy - 1 + by, cz = DIM == 3 ? iz - 1 + bz : 0;
-        T v = 0;
-        if (e) v = c ? c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * cz)] : (T)1;
-        cc[bz][by][bx] = v;
-      }
   // partial sums over the shared cells: offset -1 -> side 0, +1 -> side 1, 0 -> both
   T sx[3][NZ][2];
 #pragma unroll
@@ -173,6 +156,35 @@ __device__ __forceinline__ void stencil(const LvK& g, const T* __restrict__ c, i
         w0[t] = (T)g.Ae[0][p] * s;
         w1[t] = (T)g.Ae[1][p] * n1;
       }
+}
+
+
+template <int DIM, class T>
+__device__ __forceinline__ void stencil(const LvK& g, const T* __restrict__ c, int ix, int iy,
+                                        int iz, T (&w0)[DIM == 3 ? 27 : 9],
+                                        T (&w1)[DIM == 3 ? 27 : 9]) {
+  constexpr int NZ = DIM == 3 ? 2 : 1;
+  T cc[NZ][2][2];  // [bz][by][bx]
+  bool ex[2], ey[2], ez[2];
+  ex[0] = ix - 1 >= 0;
+  ex[1] = ix < g.n[0];
+  ey[0] = iy - 1 >= 0;
+  ey[1] = iy < g.n[1];
+  ez[0] = DIM == 2 ? true : iz - 1 >= 0;
+  ez[1] = DIM == 2 ? true : iz < g.n[2];
+#pragma unroll
+  for (int bz = 0; bz < NZ; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const bool e = ex[bx] && ey[by] && (DIM == 2 || ez[bz]);
+        const int cx = ix - 1 + bx, cy = iy - 1 + by, cz = DIM == 3 ? iz - 1 + bz : 0;
+        T v = 0;
+        if (e) v = c ? c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * cz)] : (T)1;
+        cc[bz][by][bx] = v;
+      }
+  stencil_weights<DIM, T>(g, cc, ex, ey, ez, w0, w1);
 }
 
 // (A x)_i for both blocks and the two diagonals.
@@ -439,6 +451,127 @@ __global__ void __launch_bounds__(kT)
   x.x += w * a0;
   x.y += w * a1;
   xf[i] = x;
+}
+
+
+// ----------------------------------------------------------------- 2.5-D stencil kernels (3-D)
+// A workgroup owns a 32 x 8 tile of node columns and marches through up to
+// 32 node planes in z.  The iterate x (tile plus a one-node halo) is staged
+// plane by plane in a 3-plane LDS ring and the cell coefficients in a 2-plane
+// ring, so each value is fetched from memory about once per sweep instead of
+// once per stencil use.
+constexpr int SBX = 32, SBY = 8, SKZ = 32;
+
+// OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
+// writing the FP64 interleaved z64 (last step of the V-cycle).
+template <class T, int OP>
+__global__ void __launch_bounds__(SBX * SBY)
+    k_stencil3(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
+               const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ out,
+               typename V2<T>::type* __restrict__ d, T al0, T al1, T be0, T be1,
+               double2* __restrict__ z64) {
+  using T2 = typename V2<T>::type;
+  __shared__ T2 xs[3][SBY + 2][SBX + 2];
+  __shared__ T cs[2][SBY + 1][SBX + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid % SBX, ty = tid / SBX;
+  const int x0 = blockIdx.x * SBX, y0 = blockIdx.y * SBY, z0 = blockIdx.z * SKZ;
+  const int ix = x0 + tx, iy = y0 + ty;
+  const bool inside = ix < g.nn[0] && iy < g.nn[1];
+  const int zend = min(z0 + SKZ, g.nn[2]);
+
+  auto load_x = [&](int slot, int z) {
+    for (int q = tid; q < (SBX + 2) * (SBY + 2); q += SBX * SBY) {
+      const int hx = q % (SBX + 2), hy = q / (SBX + 2);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+      T2 v;
+      v.x = 0;
+      v.y = 0;
+      if (z >= 0 && z < g.nn[2] && gx >= 0 && gx < g.nn[0] && gy >= 0 && gy < g.nn[1])
+        v = x[gx + (long long)g.nn[0] * (gy + (long long)g.nn[1] * z)];
+      xs[slot][hy][hx] = v;
+    }
+  };
+  auto load_c = [&](int slot, int zc) {
+    for (int q = tid; q < (SBX + 1) * (SBY + 1); q += SBX * SBY) {
+      const int hx = q % (SBX + 1), hy = q / (SBX + 1);
+      const int cx = x0 - 1 + hx, cy = y0 - 1 + hy;
+      T v = 0;
+      if (zc >= 0 && zc < g.n[2] && cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1])
+        v = c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * zc)];
+      cs[slot][hy][hx] = v;
+    }
+  };
+  // ring slots: node plane z lives in slot (z - z0 + 1) % 3, cell plane zc in (zc - z0 + 1) & 1
+  load_x(0, z0 - 1);
+  load_x(1, z0);
+  load_c(0, z0 - 1);
+  for (int z = z0; z < zend; ++z) {
+    const int k = z - z0;
+    const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
+    const int cm = k & 1, cp = cm ^ 1;
+    load_x(sp, z + 1);
+    load_c(cp, z);
+    __syncthreads();
+    if (inside) {
+      T cc[2][2][2];
+      bool ex[2], ey[2], ez[2];
+      ex[0] = ix - 1 >= 0;
+      ex[1] = ix < g.n[0];
+      ey[0] = iy - 1 >= 0;
+      ey[1] = iy < g.n[1];
+      ez[0] = z - 1 >= 0;
+      ez[1] = z < g.n[2];
+#pragma unroll
+      for (int by = 0; by < 2; ++by)
+#pragma unroll
+        for (int bx = 0; bx < 2; ++bx) {
+          cc[0][by][bx] = cs[cm][ty + by][tx + bx];
+          cc[1][by][bx] = cs[cp][ty + by][tx + bx];
+        }
+      T w0[27], w1[27];
+      stencil_weights<3, T>(g, cc, ex, ey, ez, w0, w1);
+      T y0 = 0, y1 = 0;
+      const int sl[3] = {sm, s0, sp};
+#pragma unroll
+      for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+        for (int tyy = 0; tyy < 3; ++tyy)
+#pragma unroll
+          for (int txx = 0; txx < 3; ++txx) {
+            const T2 v = xs[sl[tz]][ty + tyy][tx + txx];
+            const int t = txx + 3 * tyy + 9 * tz;
+            y0 += w0[t] * v.x;
+            y1 += w1[t] * v.y;
+          }
+      const long long i = ix + (long long)g.nn[0] * (iy + (long long)g.nn[1] * z);
+      const T2 bb = b[i];
+      const T r0 = bb.x - y0, r1 = bb.y - y1;
+      if (OP == 0) {
+        T2 o;
+        o.x = r0;
+        o.y = r1;
+        out[i] = o;
+      } else {
+        const T2 xi = xs[s0][ty + 1][tx + 1];
+        const T2 dv = d[i];
+        const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / w0[13];
+        const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / w1[13];
+        if (OP == 2) {
+          z64[i] = make_double2((double)(xi.x + dn0), (double)(xi.y + dn1));
+        } else {
+          T2 dn, xo;
+          dn.x = dn0;
+          dn.y = dn1;
+          xo.x = xi.x + dn0;
+          xo.y = xi.y + dn1;
+          d[i] = dn;
+          out[i] = xo;
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // Coarsest level: COARSE_DEGREE Chebyshev steps for both blocks by one
@@ -726,10 +859,26 @@ int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) 
   return PF_OK;
 }
 
+// Levels whose x rows span at least one tile use the 2.5-D kernels.
+inline bool use_tiled(const LvK& k, int dim) { return dim == 3 && k.nn[0] >= SBX && k.nn[1] >= SBY; }
+
+inline dim3 tiled_grid(const LvK& k) {
+  return dim3((k.nn[0] + SBX - 1) / SBX, (k.nn[1] + SBY - 1) / SBY, (k.nn[2] + SKZ - 1) / SKZ);
+}
+
 template <int DIM, class T, int IN, int OUT>
 int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::type* x_out,
                 const double* al, const double* be, int k, const double* r64, double* z64,
                 hipStream_t s) {
+  if (IN == 2 && use_tiled(L.k, DIM)) {
+    constexpr int OP = OUT == 1 ? 2 : 1;
+    hipLaunchKernelGGL((k_stencil3<T, OP>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+                       (const T*)L.c, (const typename V2<T>::type*)L.b, x_in, x_out, L.d,
+                       (T)al[2 * k], (T)al[2 * k + 1], (T)be[2 * k], (T)be[2 * k + 1],
+                       reinterpret_cast<double2*>(z64));
+    PF_HIP_CHECK(hipGetLastError());
+    return PF_OK;
+  }
   hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
                      (const T*)L.c, L.b, x_in, x_out, L.d, (T)al[2 * k], (T)al[2 * k + 1],
                      (T)be[2 * k], (T)be[2 * k + 1], reinterpret_cast<const double2*>(r64),
@@ -802,9 +951,16 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   if (top) PF_TRY((smooth_step<DIM, T, 1, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
   else PF_TRY((smooth_step<DIM, T, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
   PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
-  hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
-                     (const T*)L.c, (const typename V2<T>::type*)L.b,
-                     (const typename V2<T>::type*)L.xb, L.r);
+  if (use_tiled(L.k, DIM)) {
+    hipLaunchKernelGGL((k_stencil3<T, 0>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+                       (const T*)L.c, (const typename V2<T>::type*)L.b,
+                       (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
+                       nullptr);
+  } else {
+    hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+                       (const T*)L.c, (const typename V2<T>::type*)L.b,
+                       (const typename V2<T>::type*)L.xb, L.r);
+  }
   PF_HIP_CHECK(hipGetLastError());
   Level<T>& C = H.lv[l + 1];
   hipLaunchKernelGGL((k_restrict<DIM, T>), dim3(blocks(C.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
@@ -856,6 +1012,17 @@ hipError_t pc_free(pf_problem* pb) {
   delete st;
   pb->pc = nullptr;
   return first;
+}
+
+double* pc_coef_buffer(pf_problem* pb) { return static_cast<PcState*>(pb->pc)->coef0; }
+
+int pc_setup_prepared(pf_problem* pb, int kind, int precision, hipStream_t s) {
+  PcState* st = static_cast<PcState*>(pb->pc);
+  pb->pc_kind = kind;
+  pb->pc_precision = precision;
+  if (kind == PF_PC_NONE || kind == PF_PC_JACOBI) return PF_OK;
+  if (precision == PF_FP32) return setup_gmg<float>(pb, st, st->h32, s);
+  return setup_gmg<double>(pb, st, st->h64, s);
 }
 
 int pc_setup(pf_problem* pb, const double* U, int kind, int precision, hipStream_t s) {

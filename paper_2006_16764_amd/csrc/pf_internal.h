@@ -49,20 +49,23 @@ struct Geo {
 Geo make_geo(const pf_params& p);
 
 // Element-loop modes of the residual kernel family.
-enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3 };
+// MODE_VJPU: (dF/dU)^T w only (the operator of the transposed Krylov solve).
+enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4 };
 
 // 3-D single-pass kernels (pf_fused3.hip).
 long long fused3_side_len(const Geo& G);
 int fused3_tiles(const Geo& G);
 int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
                   const double* F0, const double* eps_dev, double* out0, double* out1,
-                  double* vjp_part, hipStream_t s);
+                  double* vjp_part, double* coef, hipStream_t s);
 
 // Launch helpers (defined in pf_residual.hip).
+// coef (optional, residual mode only): receives the cell mean of a(grad phi)^2,
+// the coefficient of the preconditioner's phi block.
 int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
                            const double* v, const double* F0, const double* eps_dev,
                            double* out0, double* out1, double* gparams_partial,
-                           hipStream_t s);
+                           hipStream_t s, double* coef = nullptr);
 
 // ----------------------------------------------------------------- BLAS-1 (pf_blas.hip)
 // Deterministic reductions over n doubles: fixed grid, fixed order.
@@ -80,6 +83,9 @@ int blas_axpby(double a, const double* x, double b, const double* y, double* z, 
                hipStream_t s);
 int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, double* eps_dev,
                 hipStream_t s);
+// eps from a precomputed |U|^2 (device scalar) and |v|^2 computed here
+int blas_fd_eps_cached(pf_problem* pb, const double* unorm2_dev, const double* v, long long n,
+                       double* eps_dev, hipStream_t s);
 int blas_reduce_partials(const double* partials, int nparts, int k, double* out_dev,
                          double scale, hipStream_t s);
 int blas_sub_scalars(double* acc_dev, const double* x_dev, int k, hipStream_t s);
@@ -89,6 +95,10 @@ struct GmgLevel;
 int pc_alloc(pf_problem* pb);
 hipError_t pc_free(pf_problem* pb);
 int pc_setup(pf_problem* pb, const double* U, int kind, int precision, hipStream_t s);
+// Setup from cell coefficients already written (by a residual evaluation at the
+// same state) into pc_coef_buffer(pb).
+int pc_setup_prepared(pf_problem* pb, int kind, int precision, hipStream_t s);
+double* pc_coef_buffer(pf_problem* pb);
 int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s);
 
 // ----------------------------------------------------------------- misc kernels

@@ -37,7 +37,7 @@ template <int DIM, int MODE>
 __global__ void __launch_bounds__(kElemBlock)
     k_elem(Geo G, const double2* __restrict__ U, const double2* __restrict__ Up,
            const double2* __restrict__ V, const double* __restrict__ eps_dev,
-           double* __restrict__ E, double* __restrict__ vjp_part) {
+           double* __restrict__ E, double* __restrict__ vjp_part, double* __restrict__ coef) {
   constexpr int NA = 1 << DIM;
   constexpr int NO = (MODE == MODE_VJP) ? 4 : 2;
   const long long e = (long long)blockIdx.x * kElemBlock + threadIdx.x;
@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(kElemBlock)
     }
     double out[NO][NA];
     Element<DIM, MODE>::run(G, u0, u1, p0, p1, v0, v1, out, ge, gl);
+    if (MODE == MODE_RES && coef) coef[e] = ge / ((double)NA * G.jac);
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
@@ -152,7 +153,7 @@ __global__ void __launch_bounds__(256)
 template <int DIM>
 int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
                const double* F0, const double* eps_dev, double* out0, double* out1,
-               double* vjp_part, hipStream_t s) {
+               double* vjp_part, double* coef, hipStream_t s) {
   const Geo& G = pb->geo;
   const unsigned eb = (unsigned)((G.n_elems + kElemBlock - 1) / kElemBlock);
   const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
@@ -162,19 +163,23 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
   switch (mode) {
     case MODE_RES:
       hipLaunchKernelGGL((k_elem<DIM, MODE_RES>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2,
-                         nullptr, nullptr, pb->elem_buf, nullptr);
+                         nullptr, nullptr, pb->elem_buf, nullptr, coef);
       break;
     case MODE_FD:
       hipLaunchKernelGGL((k_elem<DIM, MODE_FD>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
-                         eps_dev, pb->elem_buf, nullptr);
+                         eps_dev, pb->elem_buf, nullptr, nullptr);
       break;
     case MODE_JVP:
       hipLaunchKernelGGL((k_elem<DIM, MODE_JVP>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
-                         nullptr, pb->elem_buf, nullptr);
+                         nullptr, pb->elem_buf, nullptr, nullptr);
+      break;
+    case MODE_VJPU:
+      hipLaunchKernelGGL((k_elem<DIM, MODE_VJPU>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
+                         nullptr, pb->elem_buf, nullptr, nullptr);
       break;
     default:
       hipLaunchKernelGGL((k_elem<DIM, MODE_VJP>), dim3(eb), dim3(kElemBlock), 0, s, G, U2, P2, V2,
-                         nullptr, pb->elem_buf, vjp_part);
+                         nullptr, pb->elem_buf, vjp_part, nullptr);
       break;
   }
   PF_HIP_CHECK(hipGetLastError());
@@ -195,10 +200,11 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
 
 int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
                            const double* v, const double* F0, const double* eps_dev,
-                           double* out0, double* out1, double* vjp_part, hipStream_t s) {
+                           double* out0, double* out1, double* vjp_part, hipStream_t s,
+                           double* coef) {
   if (pb->geo.dim == 3)
-    return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
-  return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, s);
+    return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
+  return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
 }
 
 // Number of per-block partial sums the VJP writes (one per workgroup).
