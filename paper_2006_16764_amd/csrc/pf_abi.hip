@@ -209,27 +209,48 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
       const double wsq = hp[j + 1];
       double hn;
       if (wsq - hsq > 0.5 * wsq) {
-        // less than half the norm lost: one pass is orthogonal to working accuracy
-        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nw, 1, s));
-        PF_TRY(fetch(pb, nw, 1, s));
-        hn = std::sqrt(pb->host_pinned[0]);
+        // less than half the norm removed: one projection is orthogonal to
+        // working accuracy, and |w - V h|^2 = |w|^2 - |h|^2 holds to a few
+        // ulps, so the update and the normalisation are one sweep
+        hn = std::sqrt(wsq - hsq);
+        PF_TRY(blas_axpy_scale(V, n, j + 1, h1, 1.0 / hn, w, n, s));
+      } else if (j + 1 <= kAxpyMultidotMax) {
+        // second projection (CGS2): its products come out of the first update
+        PF_TRY(blas_axpy_multidot(pb, V, n, j + 1, h1, w, n, h2, s));
+        PF_HIP_CHECK(hipMemcpyAsync(hp + 64, h2, (j + 2) * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+        PF_HIP_CHECK(hipStreamSynchronize(s));
+        double h2sq = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          H[i * m + j] += hp[64 + i];
+          h2sq += hp[64 + i] * hp[64 + i];
+        }
+        const double w2sq = hp[64 + j + 1];
+        if (h2sq <= 0.5 * w2sq) {
+          hn = std::sqrt(w2sq - h2sq);
+          if (hn > 0.0) PF_TRY(blas_axpy_scale(V, n, j + 1, h2, 1.0 / hn, w, n, s));
+        } else {
+          PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
+          PF_TRY(fetch(pb, nw, 1, s));
+          hn = std::sqrt(pb->host_pinned[0]);
+          if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
+        }
       } else {
-        // second pass (CGS2)
+        // second projection for bases beyond the fused kernel's width
         PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nullptr, 0, s));
         PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h2, s));
         PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
-        PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned + 64, h2, 65 * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
+        PF_HIP_CHECK(hipMemcpyAsync(hp + 64, h2, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
         PF_HIP_CHECK(hipStreamSynchronize(s));
         for (int i = 0; i <= j; ++i) H[i * m + j] += hp[64 + i];
         hn = std::sqrt(hp[128]);
+        if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
       }
       H[(j + 1) * m + j] = hn;
       if (!std::isfinite(hn)) {
         set_error("non-finite Arnoldi coefficient in FGMRES");
         return PF_ERR_NONFINITE;
       }
-      if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
       // Givens rotations
       for (int i = 0; i < j; ++i) {
         const double a = H[i * m + j], c = H[(i + 1) * m + j];

@@ -127,6 +127,77 @@ __global__ void __launch_bounds__(kRedThreads)
   }
 }
 
+// w <- w - sum_j coef[j] V_j (j < k) and, in the same sweep, the partials of
+// V_j . w_new (rows j < k) and of |w_new|^2 (row k): exactly the products the
+// second Gram-Schmidt projection needs, so that pass does not read V again.
+// KMAX bounds k at compile time so the accumulators stay in registers.
+template <int KMAX>
+__global__ void __launch_bounds__(kRedThreads)
+    k_axpy_multidot(const double* __restrict__ V, long long ld, int k,
+                    const double* __restrict__ coef, double* __restrict__ w, long long n,
+                    double* __restrict__ partials) {
+  __shared__ double sh[kRedThreads / 64];
+  const int nb = gridDim.x;
+  const long long n2 = n / 2;
+  double2* w2 = reinterpret_cast<double2*>(w);
+  double acc[KMAX + 1];
+#pragma unroll
+  for (int j = 0; j <= KMAX; ++j) acc[j] = 0.0;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
+       i += (long long)nb * kRedThreads) {
+    double2 a = w2[i];
+    double2 v[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < k) {
+        v[j] = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
+        const double c = coef[j];
+        a.x = fma(-c, v[j].x, a.x);
+        a.y = fma(-c, v[j].y, a.y);
+      }
+    }
+    w2[i] = a;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+      if (j < k) {
+        acc[j] = fma(v[j].x, a.x, acc[j]);
+        acc[j] = fma(v[j].y, a.y, acc[j]);
+      }
+    }
+    acc[KMAX] = fma(a.x, a.x, acc[KMAX]);
+    acc[KMAX] = fma(a.y, a.y, acc[KMAX]);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      const double t = block_sum(acc[j], sh);
+      if (threadIdx.x == 0) partials[(long long)j * nb + blockIdx.x] = t;
+    }
+  }
+  const double t = block_sum(acc[KMAX], sh);
+  if (threadIdx.x == 0) partials[(long long)k * nb + blockIdx.x] = t;
+}
+
+// w <- scale * (w - sum_j coef[j] V_j)
+__global__ void __launch_bounds__(256)
+    k_axpy_scale(const double* __restrict__ V, long long ld, int k,
+                 const double* __restrict__ coef, double scale, double* __restrict__ w,
+                 long long n) {
+  const long long n2 = n / 2;
+  double2* w2 = reinterpret_cast<double2*>(w);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    double2 a = w2[i];
+    for (int j = 0; j < k; ++j) {
+      const double c = coef[j];
+      const double2 v = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
+      a.x = fma(-c, v.x, a.x);
+      a.y = fma(-c, v.y, a.y);
+    }
+    w2[i] = make_double2(scale * a.x, scale * a.y);
+  }
+}
+
 // y = x * alpha (invert = 0) or x / alpha (invert = 1), alpha on the device
 __global__ void __launch_bounds__(256)
     k_scale(const double* __restrict__ x, const double* __restrict__ alpha, int invert,
@@ -206,6 +277,35 @@ int blas_axpy_dot(pf_problem* pb, const double* V, long long ld, int k, const do
                        1.0);
     PF_HIP_CHECK(hipGetLastError());
   }
+  return PF_OK;
+}
+
+int blas_axpy_multidot(pf_problem* pb, const double* V, long long ld, int k,
+                       const double* coef_dev, double* w, long long n, double* out_dev,
+                       hipStream_t s) {
+  if (k < 1 || k > kAxpyMultidotMax) return PF_ERR_INVALID_ARG;
+  const int nb = pb->n_red_blocks;
+  if (k <= 8)
+    hipLaunchKernelGGL(k_axpy_multidot<8>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k, coef_dev,
+                       w, n, pb->red_partials);
+  else if (k <= 16)
+    hipLaunchKernelGGL(k_axpy_multidot<16>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k,
+                       coef_dev, w, n, pb->red_partials);
+  else
+    hipLaunchKernelGGL(k_axpy_multidot<32>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k,
+                       coef_dev, w, n, pb->red_partials);
+  PF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(kRedThreads), 0, s, pb->red_partials, nb,
+                     out_dev, 1.0);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+int blas_axpy_scale(const double* V, long long ld, int k, const double* coef_dev, double scale,
+                    double* w, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_scale, dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, s, V, ld, k,
+                     coef_dev, scale, w, n);
+  PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }
 

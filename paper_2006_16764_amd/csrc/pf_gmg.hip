@@ -455,12 +455,18 @@ __global__ void __launch_bounds__(kT)
 
 
 // ----------------------------------------------------------------- 2.5-D stencil kernels (3-D)
-// A workgroup owns a 32 x 8 tile of node columns and marches through up to
-// 32 node planes in z.  The iterate x (tile plus a one-node halo) is staged
-// plane by plane in a 3-plane LDS ring and the cell coefficients in a 2-plane
-// ring, so each value is fetched from memory about once per sweep instead of
-// once per stencil use.
+// A workgroup owns a 32 x 8 tile of node columns and marches through kz node
+// planes in z.  The iterate x (tile plus a one-node halo) is staged plane by
+// plane in a 3-plane LDS ring and the cell coefficients in a 2-plane ring, so
+// each value is fetched from memory about once per sweep instead of once per
+// stencil use.  kz is chosen per level: long marches on the finest level, short
+// ones on coarse levels, whose few tiles would otherwise leave most compute
+// units idle while a handful of workgroups step through their planes.
 constexpr int SBX = 32, SBY = 8, SKZ = 32;
+#ifndef PF_TILED_MIN_GROUPS
+#define PF_TILED_MIN_GROUPS 4096
+#endif
+constexpr long long kTiledMinGroups = PF_TILED_MIN_GROUPS;
 
 // OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
 // writing the FP64 interleaved z64 (last step of the V-cycle).
@@ -469,16 +475,16 @@ __global__ void __launch_bounds__(SBX * SBY)
     k_stencil3(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
                const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ out,
                typename V2<T>::type* __restrict__ d, T al0, T al1, T be0, T be1,
-               double2* __restrict__ z64) {
+               double2* __restrict__ z64, int kz) {
   using T2 = typename V2<T>::type;
   __shared__ T2 xs[3][SBY + 2][SBX + 2];
   __shared__ T cs[2][SBY + 1][SBX + 1];
   const int tid = threadIdx.x;
   const int tx = tid % SBX, ty = tid / SBX;
-  const int x0 = blockIdx.x * SBX, y0 = blockIdx.y * SBY, z0 = blockIdx.z * SKZ;
+  const int x0 = blockIdx.x * SBX, y0 = blockIdx.y * SBY, z0 = blockIdx.z * kz;
   const int ix = x0 + tx, iy = y0 + ty;
   const bool inside = ix < g.nn[0] && iy < g.nn[1];
-  const int zend = min(z0 + SKZ, g.nn[2]);
+  const int zend = min(z0 + kz, g.nn[2]);
 
   auto load_x = [&](int slot, int z) {
     for (int q = tid; q < (SBX + 2) * (SBY + 2); q += SBX * SBY) {
@@ -862,8 +868,18 @@ int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) 
 // Levels whose x rows span at least one tile use the 2.5-D kernels.
 inline bool use_tiled(const LvK& k, int dim) { return dim == 3 && k.nn[0] >= SBX && k.nn[1] >= SBY; }
 
+// z-march length: the longest power of two up to SKZ that still gives at
+// least kTiledMinGroups workgroups
+inline int tiled_kz(const LvK& k) {
+  const long long tiles = (long long)((k.nn[0] + SBX - 1) / SBX) * ((k.nn[1] + SBY - 1) / SBY);
+  int kz = SKZ;
+  while (kz > 1 && tiles * ((k.nn[2] + kz - 1) / kz) < kTiledMinGroups) kz /= 2;
+  return kz;
+}
+
 inline dim3 tiled_grid(const LvK& k) {
-  return dim3((k.nn[0] + SBX - 1) / SBX, (k.nn[1] + SBY - 1) / SBY, (k.nn[2] + SKZ - 1) / SKZ);
+  const int kz = tiled_kz(k);
+  return dim3((k.nn[0] + SBX - 1) / SBX, (k.nn[1] + SBY - 1) / SBY, (k.nn[2] + kz - 1) / kz);
 }
 
 template <int DIM, class T, int IN, int OUT>
@@ -875,7 +891,7 @@ int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::t
     hipLaunchKernelGGL((k_stencil3<T, OP>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b, x_in, x_out, L.d,
                        (T)al[2 * k], (T)al[2 * k + 1], (T)be[2 * k], (T)be[2 * k + 1],
-                       reinterpret_cast<double2*>(z64));
+                       reinterpret_cast<double2*>(z64), tiled_kz(L.k));
     PF_HIP_CHECK(hipGetLastError());
     return PF_OK;
   }
@@ -955,7 +971,7 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
     hipLaunchKernelGGL((k_stencil3<T, 0>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,
                        (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
-                       nullptr);
+                       nullptr, tiled_kz(L.k));
   } else {
     hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,

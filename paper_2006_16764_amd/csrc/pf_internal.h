@@ -75,6 +75,15 @@ int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const do
                   long long n, double* out_dev, hipStream_t s);
 int blas_axpy_dot(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
                   double* w, long long n, double* dots_dev, int want_norm, hipStream_t s);
+// w <- w - V coef (k vectors) and out[0..k-1] = V^T w_new, out[k] = |w_new|^2,
+// one sweep; k <= kAxpyMultidotMax
+constexpr int kAxpyMultidotMax = 32;
+int blas_axpy_multidot(pf_problem* pb, const double* V, long long ld, int k,
+                       const double* coef_dev, double* w, long long n, double* out_dev,
+                       hipStream_t s);
+// w <- scale * (w - V coef), one sweep
+int blas_axpy_scale(const double* V, long long ld, int k, const double* coef_dev, double scale,
+                    double* w, long long n, hipStream_t s);
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
                  double* x, long long n, hipStream_t s);
 int blas_scale_copy(const double* x, const double* alpha_dev, int invert, double* y,
