@@ -3,17 +3,24 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The discrete residual follows the paper's Galerkin weak form (Sec. 2.1.1,
-Eqs. rpf and rtemp) discretised in time by the theta-method with theta = 1
-(backward Euler, Sec. 2.1.2, Eqs. dpf, dtemp, theta).  The phi equation is the
-lambda-coupled form of Sec. 4.2 (Eqs. pf2 and lambda) for a pure substance,
+Eqs. rpf and rtemp) discretised in time by the weighted (theta) method of
+Sec. 2.1.2 (Eqs. dpf, dtemp and theta); theta = 1 is backward Euler.  The phi
+equation is the lambda-coupled form of Sec. 4.2 (Eqs. pf2 and lambda) for a pure substance,
 i.e. with the factor 1 + (1 - k) u equal to one and no frozen-temperature term;
 the u equation is the thermal equation of Sec. 4.1 (Eq. temp1) with latent heat
 source 1/2 phi_t because phi spans [-1, 1].  Readings of garbled or silent
 passages are listed where they are used:
 
-  F1_i = (a(grad phi)^2 (phi - phi^n)/dt, psi_i) + (J(grad phi), grad psi_i)
-         - (phi - phi^3 - lambda (1 - phi^2)^2 u, psi_i)
-  F2_i = ((u - u^n)/dt - (phi - phi^n)/(2 dt), psi_i) + (D grad u, grad psi_i)
+  F1_i = (a(grad phi)^2 (phi - phi^n)/dt, psi_i)
+         + theta [ (J(grad phi), grad psi_i) - (phi - phi^3 - lambda (1 - phi^2)^2 u, psi_i) ]
+         + (1 - theta) [ the same two terms at U^n ]
+  F2_i = ((u - u^n)/dt, psi_i) + theta (D grad u, grad psi_i)
+         + (1 - theta) (D grad u^n, grad psi_i) - (phihat/2, psi_i)
+  phihat = theta (phi - phi^n)/dt + (1 - theta) (phi^n - phi^(n-1))/dt
+
+`residual` returns the part that depends on the new state U (the theta-weighted
+terms); `theta_explicit` returns the terms fixed by U^n and U^(n-1), so the
+step solves residual(U) + theta_explicit = 0.  With theta = 1 the latter is zero.
 
   a(g) = 1 - 3 eps4 + 4 eps4 S / (q + delta2)^2,  q = sum g_k^2, S = sum g_k^4
   J(g) = d/dg [ a(g)^2 q / 2 ] = a^2 g + a q da/dg
@@ -25,8 +32,10 @@ passages are listed where they are used:
   term twice in two inconsistent forms (Eqs. pf1 and pf2).
 * The coupling term multiplies only the lambda part of G3 by u (Eq. lambda with
   the product G3 (u + G4) read as phi - phi^3 - lambda (1 - phi^2)^2 (u + G4)).
-* The time term is a(U^{n+1})^2 (phi^{n+1} - phi^n)/dt, the backward-Euler
-  discretisation of tau(n) phi_t.
+* The time term is a(U^{n+1})^2 (phi^{n+1} - phi^n)/dt, the discretisation of
+  tau(n) phi_t with the mobility factor taken at the new state.
+* phihat is the paper's theta-weighted rate (Eq. theta); the first step of a
+  run, which has no phi^(n-1), takes phi^(n-1) = phi^n.
 * Zero-Neumann boundaries are natural: no boundary integrals (Sec. 2.1).
 * 3 Gauss points per direction: 9 in 2-D, 27 in 3-D (Secs. 4.1 and 4.2).
 
@@ -55,6 +64,7 @@ class Params:
     lam: float
     D: float
     delta2: float = 1e-16
+    theta: float = 1.0
 
 
 class Mesh:
@@ -185,11 +195,11 @@ def element_residual(el: Element, phi_e, u_e, phin_e, un_e, p: Params):
         dphi = dphi_e @ N
         du = du_e @ N
         a = anisotropy(g, p)
-        J = flux(g, p)
-        s1 = a * a * dphi / p.dt - reaction(phi, u, p)
-        s2 = (du - 0.5 * dphi) / p.dt
+        J = p.theta * flux(g, p)
+        s1 = a * a * dphi / p.dt - p.theta * reaction(phi, u, p)
+        s2 = (du - 0.5 * p.theta * dphi) / p.dt
         F1 = F1 + el.W[q] * (s1[:, None] * N[None, :] + J @ dN.T)
-        F2 = F2 + el.W[q] * (s2[:, None] * N[None, :] + (p.D * gu) @ dN.T)
+        F2 = F2 + el.W[q] * (s2[:, None] * N[None, :] + (p.theta * p.D * gu) @ dN.T)
     return F1, F2
 
 
@@ -226,3 +236,30 @@ def lumped_mass(mesh: Mesh) -> np.ndarray:
     m = np.zeros(mesh.n_nodes)
     np.add.at(m, conn, np.broadcast_to(me, conn.shape))
     return m
+
+
+def mass_apply(mesh: Mesh, x) -> np.ndarray:
+    """(M x)_i = sum_j (psi_j, psi_i) x_j by element quadrature (consistent mass)."""
+    el = Element(mesh)
+    conn = mesh.connectivity()
+    Me = (el.N * el.W[:, None]).T @ el.N  # [2^dim, 2^dim]
+    x = np.asarray(x)
+    y = np.zeros(mesh.n_nodes, dtype=x.dtype)
+    np.add.at(y, conn, x[conn] @ Me.T)
+    return y
+
+
+def theta_explicit(mesh: Mesh, Un, Unm1, p: Params) -> np.ndarray:
+    """Terms of the theta step fixed by U^n and U^(n-1), interleaved [n_nodes, 2].
+
+    (1 - theta) times the spatial operator at U^n (the theta = 1 residual with
+    U = U^n = previous state, whose time terms vanish), minus the history half
+    of the latent source, (1 - theta)/(2 dt) (phi^n - phi^(n-1), psi_i), on the
+    u rows (Eqs. dpf, dtemp and theta).
+    """
+    Un = np.asarray(Un).reshape(-1, 2)
+    Unm1 = np.asarray(Unm1).reshape(-1, 2)
+    G = residual(mesh, Un, Un, dataclasses.replace(p, theta=1.0))
+    E = (1.0 - p.theta) * G
+    E[:, 1] -= (1.0 - p.theta) / (2.0 * p.dt) * mass_apply(mesh, Un[:, 0] - Unm1[:, 0])
+    return E

@@ -210,7 +210,7 @@ class BlockPreconditioner:
         self.kind = kind
         c = cell_coefficient(mesh, U, p)
         ones = np.ones(mesh.n_elems)
-        self.blocks = [(c, 1.0 / p.dt, 1.0), (ones, 1.0 / p.dt, p.D)]
+        self.blocks = [(c, 1.0 / p.dt, p.theta), (ones, 1.0 / p.dt, p.theta * p.D)]
         if kind == "jacobi":
             self.dinv = [1.0 / assemble(mesh, cb, sm, sk).diagonal() for cb, sm, sk in self.blocks]
         else:

@@ -8,8 +8,9 @@ a sparse direct factorisation, update U_{l+1} = U_l + Lambda dU
 ||F(U_l + Lambda dU)|| <= ||F(U_l)|| (Eq. glob), and stop once
 ||F(U_l)|| < tau_r ||F(U_0)|| + tau_a (Eq. tolerance).
 
-Backward-Euler stepping: U^{k+1} solves F(U^{k+1}; U^k) = 0 with U^k as the
-initial guess, fixed dt (Sec. 2.1.2).
+Time stepping: U^{k+1} solves F(U^{k+1}; U^k) = 0 with U^k as the initial
+guess, fixed dt (Sec. 2.1.2); for theta < 1 F includes the terms fixed by U^k
+and U^{k-1} (fem.theta_explicit).  The adjoint below is that of backward Euler.
 
 Discrete adjoint of L(U^K) subject to F(U^k; U^{k-1}, p) = 0, k = 1..K
 (a gradient the paper does not compute; the Lagrangian identities are
@@ -25,7 +26,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from . import deriv
-from .fem import Mesh, Params, lumped_mass, residual
+from .fem import Mesh, Params, lumped_mass, residual, theta_explicit
 
 
 @dataclasses.dataclass
@@ -72,10 +73,17 @@ def newton(mesh: Mesh, U0, Uprev, p: Params, tau_r: float = 1e-10, tau_a: float 
 
 
 def evolve(mesh: Mesh, U0, p: Params, steps: int, tau_r: float = 1e-10) -> List[np.ndarray]:
-    """States [U^0, U^1, ..., U^steps] of backward-Euler stepping."""
+    """States [U^0, U^1, ..., U^steps] of theta-method stepping (Sec. 2.1.2).
+
+    Each step solves residual(U; U^n) + theta_explicit(U^n, U^(n-1)) = 0 from
+    U^n; the first step takes U^(n-1) = U^0.
+    """
     states = [np.array(U0, dtype=float).reshape(-1, 2)]
-    for _ in range(steps):
-        U, _ = newton(mesh, states[-1], states[-1], p, tau_r=tau_r)
+    for k in range(steps):
+        load = None
+        if p.theta != 1.0:
+            load = -theta_explicit(mesh, states[k], states[max(k - 1, 0)], p)
+        U, _ = newton(mesh, states[-1], states[-1], p, tau_r=tau_r, load=load)
         states.append(U)
     return states
 
@@ -92,6 +100,8 @@ def misfit(mesh: Mesh, U, phi_target) -> Tuple[float, np.ndarray]:
 
 def adjoint_gradient(mesh: Mesh, states: List[np.ndarray], p: Params, phi_target):
     """(L, dL/d eps4, dL/d lam) for L = misfit(U^K) by the discrete adjoint."""
+    if p.theta != 1.0:
+        raise ValueError("the oracle adjoint covers backward Euler (theta = 1) only")
     K = len(states) - 1
     L, mu = misfit(mesh, states[K], phi_target)
     ge = 0.0
