@@ -5,17 +5,26 @@
  *
  * Problem (paper Sec. 2): nodal Q1 finite elements on a structured box mesh
  * [-L0,L0] x [-L1,L1] (x [-L2,L2]) with n[k] elements and n[k]+1 nodes per
- * axis, two fields per node (phi, u), backward Euler in time.  The discrete
- * residual F(U; U^n) is
+ * axis, two fields per node (phi, u), the weighted (theta) method in time
+ * (Sec. 2.1.2, Eqs. dpf, dtemp, theta; theta = 1 is backward Euler).  The
+ * residual of the step from U^n (and U^(n-1)) to U is F(U; U^n) + E(U^n, U^(n-1))
+ * with the part that depends on U
  *
- *   F1_i = (a^2 (phi - phi^n)/dt, psi_i) + (J(grad phi), grad psi_i)
- *          - (phi - phi^3 - lambda (1 - phi^2)^2 u, psi_i)
- *   F2_i = ((u - u^n)/dt - (phi - phi^n)/(2 dt), psi_i) + (D grad u, grad psi_i)
+ *   F1_i = (a^2 (phi - phi^n)/dt, psi_i)
+ *          + theta [ (J(grad phi), grad psi_i) - (phi - phi^3 - lambda (1 - phi^2)^2 u, psi_i) ]
+ *   F2_i = ((u - u^n)/dt - theta (phi - phi^n)/(2 dt), psi_i) + theta (D grad u, grad psi_i)
+ *
+ * and the part fixed by the previous states (zero when theta = 1)
+ *
+ *   E_i = (1 - theta) [ the spatial terms of F at U^n ]
+ *         - (1 - theta) ((phi^n - phi^(n-1))/(2 dt), psi_i)  on the u rows,
  *
  * with the fourfold anisotropy a(g) = 1 - 3 eps4 + 4 eps4 sum g_k^4/(|g|^2 +
  * delta2)^2 (Eq. gs), J(g) = d/dg (a^2 |g|^2 / 2) (the variational form of the
  * anisotropic terms of Eq. pf2), the lambda coupling of Eq. lambda, the thermal
- * equation of Eq. temp1 and 3 Gauss points per axis (Secs. 4.1, 4.2).
+ * equation of Eq. temp1 with the latent rate of Eq. theta, and 3 Gauss points
+ * per axis (Secs. 4.1, 4.2).  The mobility factor a^2 of the time term is taken
+ * at the new state.
  *
  * Vector layout: every state, residual and direction vector is a DEVICE array
  * of 2 * n_nodes doubles, interleaved node-major: V[2*node + 0] = phi part,
@@ -64,7 +73,9 @@ extern "C" {
 
 /* Model and mesh.  dim = 2 or 3; n[k] >= 1 elements per axis (n[2] ignored
  * in 2-D); half_width[k] > 0.  dt > 0, D > 0, delta2 > 0 (regularises the
- * anisotropy where grad phi = 0; 1e-16 is the default reading). */
+ * anisotropy where grad phi = 0; 1e-16 is the default reading); theta in
+ * (0, 1]: the time weight of Eq. dpf (1 backward Euler, 1/2 the trapezoidal
+ * or Crank-Nicolson rule). */
 typedef struct {
   int dim;
   int n[3];
@@ -74,6 +85,7 @@ typedef struct {
   double lambda;
   double D;
   double delta2;
+  double theta;
 } pf_params;
 
 /* Newton-Krylov options (Sec. 2.2).  The forcing term follows Eqs. force1 to
@@ -130,17 +142,24 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out);
 /* Free the handle and its workspaces (synchronises the device). */
 int pf_destroy(pf_problem* pb);
 
-/* Replace the scalar model parameters (dt, eps4, lambda, D, delta2) of an
+/* Replace the scalar model parameters (dt, eps4, lambda, D, delta2, theta) of an
  * existing handle; mesh fields of params must match the handle.  Host only. */
 int pf_set_params(pf_problem* pb, const pf_params* params);
 
 /* Number of nodes and of unknowns (2 * nodes) of the handle's mesh. */
 long long pf_num_nodes(const pf_problem* pb);
 
-/* [async] F = F(U; Uprev), the residual above (Sec. 2.1.2, Eqs. dpf, dtemp
- * with theta = 1).  U, Uprev, F: device, 2*n_nodes doubles.  F must not alias
- * U or Uprev. */
+/* [async] F = F(U; Uprev), the part of the step residual above that depends
+ * on U (Sec. 2.1.2, Eqs. dpf, dtemp; the whole residual when theta = 1).
+ * U, Uprev, F: device, 2*n_nodes doubles.  F must not alias U or Uprev. */
 int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F, void* stream);
+
+/* [async] E = E(Uprev, Uprev2), the part of the step residual fixed by the two
+ * previous states (Eqs. dpf, dtemp and the lagged half of the rate of Eq.
+ * theta); all zeros when theta = 1.  Uprev = U^n, Uprev2 = U^(n-1), E: device,
+ * 2*n_nodes doubles; E must not alias the inputs. */
+int pf_theta_explicit(pf_problem* pb, const double* Uprev, const double* Uprev2, double* E,
+                      void* stream);
 
 /* [async] Jacobian-vector product Jv = F'(U) v (Sec. 2.2).
  * mode PF_JV_FD: Jv = (F(U + eps v) - F0)/eps (Eq. JFmatvec) with
@@ -151,7 +170,8 @@ int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F,
 int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v,
            const double* F0, int mode, double* Jv, void* stream);
 
-/* [async] Vector-Jacobian product for the cotangent w:
+/* [async] Vector-Jacobian product of F(U; Uprev) (E held fixed) for the
+ * cotangent w:
  *   gU     = (dF/dU)^T w         (may be NULL)
  *   gUprev = (dF/dUprev)^T w     (may be NULL)
  *   gparams[0] = w . dF/d eps4, gparams[1] = w . dF/d lambda  (device, 2
@@ -182,8 +202,8 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
                     double* x, int transpose, double rtol, const pf_solver_opts* opts,
                     pf_solver_stats* stats, void* stream);
 
-/* [sync] One backward-Euler step: Newton-Krylov (Sec. 2.2) for
- * F(U; Uprev) = 0 starting from U_inout, with the forcing term, the
+/* [sync] Newton-Krylov (Sec. 2.2) for F(U; Uprev) = 0 (one backward-Euler
+ * step when theta = 1) starting from U_inout, with the forcing term, the
  * backtracking of Eq. glob (Lambda halved up to max_backtracks times), the
  * termination test of Eq. tolerance and the preconditioner rebuilt at every
  * Newton iterate.  On success U_inout holds the solution.  On failure it holds
@@ -191,11 +211,21 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
 int pf_newton_step(pf_problem* pb, const double* Uprev, double* U_inout,
                    const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
 
-/* [sync] steps backward-Euler steps from states[0]: states is a device array
- * of (steps + 1) * 2 * n_nodes doubles holding U^0 on entry; on return
- * states[k] = U^k (the checkpoints of the adjoint).  Each step starts Newton
- * from the previous state.  stats (optional) receives the last step's
- * statistics with gmres_its_total and newton_its summed over steps. */
+/* [sync] One theta-method step: as pf_newton_step for
+ * F(U; Uprev) + E(Uprev, Uprev2) = 0, with E built internally (see
+ * pf_theta_explicit; the handle keeps one extra 2*n_nodes workspace for it,
+ * allocated on first use when theta < 1).  With theta = 1 it is
+ * pf_newton_step and Uprev2 is not read. */
+int pf_newton_step_theta(pf_problem* pb, const double* Uprev2, const double* Uprev,
+                         double* U_inout, const pf_solver_opts* opts, pf_solver_stats* stats,
+                         void* stream);
+
+/* [sync] steps theta-method steps (backward Euler when theta = 1) from
+ * states[0]: states is a device array of (steps + 1) * 2 * n_nodes doubles
+ * holding U^0 on entry; on return states[k] = U^k (the checkpoints of the
+ * adjoint).  Each step starts Newton from the previous state; the first step
+ * takes U^(-1) = U^0.  stats (optional) receives the last step's statistics
+ * with gmres_its_total and newton_its summed over steps. */
 int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
               pf_solver_stats* stats, void* stream);
 
@@ -204,7 +234,8 @@ int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* o
  * the preconditioner rebuilt at U, then
  *   mu_prev = -(dF/dUprev)^T lam       (device, 2*n_nodes; may be NULL)
  *   gparams[0..1] -= (lam . dF/d eps4, lam . dF/d lambda)   (device, 2 doubles)
- * lam (device, 2*n_nodes) receives the multiplier.  rtol = opts->tau_r. */
+ * lam (device, 2*n_nodes) receives the multiplier.  rtol = opts->tau_r.
+ * Requires theta = 1 (PF_ERR_INVALID_ARG otherwise). */
 int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const double* mu,
                     double* lam, double* mu_prev, double* gparams, const pf_solver_opts* opts,
                     pf_solver_stats* stats, void* stream);

@@ -45,7 +45,7 @@ ERROR_NAMES = {
 class pf_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("half_width", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("eps4", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("D", ctypes.c_double), ("delta2", ctypes.c_double)]
+                ("D", ctypes.c_double), ("delta2", ctypes.c_double), ("theta", ctypes.c_double)]
 
 
 class pf_solver_opts(ctypes.Structure):
@@ -80,6 +80,7 @@ _SIGS = {
     "pf_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(pf_params)]),
     "pf_num_nodes": (ctypes.c_longlong, [_VP]),
     "pf_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "pf_theta_explicit": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "pf_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP]),
     "pf_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pf_precond_setup": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.c_int, _VP]),
@@ -88,6 +89,8 @@ _SIGS = {
                                        ctypes.POINTER(pf_solver_opts), ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_newton_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
                                       ctypes.POINTER(pf_solver_stats), _VP]),
+    "pf_newton_step_theta": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
+                                            ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_evolve": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.POINTER(pf_solver_opts),
                                  ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
@@ -151,7 +154,7 @@ def default_opts(**kw) -> pf_solver_opts:
     return o
 
 
-def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16) -> pf_params:
+def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16, theta=1.0) -> pf_params:
     p = pf_params()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -159,7 +162,7 @@ def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16) -> pf_params
     for k in range(3):
         p.n[k] = int(nn[k])
         p.half_width[k] = float(hw[k])
-    p.dt, p.eps4, p.lambda_, p.D, p.delta2 = dt, eps4, lam, D, delta2
+    p.dt, p.eps4, p.lambda_, p.D, p.delta2, p.theta = dt, eps4, lam, D, delta2, theta
     return p
 
 
@@ -201,6 +204,11 @@ class Problem:
         _check(load().pf_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(F), _stream(stream)), "pf_residual")
         return F
 
+    def pf_theta_explicit(self, Uprev, Uprev2, E, stream=None):
+        _check(load().pf_theta_explicit(self.h, _ptr(Uprev), _ptr(Uprev2), _ptr(E), _stream(stream)),
+               "pf_theta_explicit")
+        return E
+
     def pf_jvp(self, U, Uprev, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
         _check(load().pf_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(v), _ptr(F0), mode, _ptr(Jv),
                              _stream(stream)), "pf_jvp")
@@ -237,6 +245,17 @@ class Problem:
         d["rc"] = rc
         return d
 
+    def pf_newton_step_theta(self, Uprev2, Uprev, U, opts=None, stream=None, check=True):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        rc = load().pf_newton_step_theta(self.h, _ptr(Uprev2), _ptr(Uprev), _ptr(U), ctypes.byref(o),
+                                         ctypes.byref(st), _stream(stream))
+        if check:
+            _check(rc, "pf_newton_step_theta")
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
     def pf_evolve(self, states, steps, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
@@ -260,8 +279,9 @@ class Problem:
         _check(load().pf_dot(self.h, _ptr(x), _ptr(y), _ptr(out_dev), _stream(stream)), "pf_dot")
 
 
-def problem_for(w, gmres_m_max: int = 30, eps4=None, lam=None) -> Problem:
+def problem_for(w, gmres_m_max: int = 30, eps4=None, lam=None, theta=1.0) -> Problem:
     """Problem for an inputs.Workload (same mesh/parameter recipe)."""
     p = make_params(w.dim, [w.n] * w.dim, [w.half_width] * w.dim, w.dt,
-                    w.eps4 if eps4 is None else eps4, w.lam if lam is None else lam, w.D, w.delta2)
+                    w.eps4 if eps4 is None else eps4, w.lam if lam is None else lam, w.D, w.delta2,
+                    theta)
     return Problem(p, gmres_m_max)

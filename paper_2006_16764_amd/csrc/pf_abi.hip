@@ -57,6 +57,48 @@ __global__ void k_misfit(Geo G, const double2* __restrict__ U, const double* __r
   if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
 }
 
+// Explicit part of a theta step, second stage: E holds the spatial operator
+// at U^n; scale it by (1 - theta) and take the lagged half of the latent rate,
+// (1 - theta)/(2 dt) (M (phi^n - phi^(n-1)))_i, off the u rows.  M is the
+// consistent Q1 mass matrix, applied as the tensor product of the assembled
+// 1-D rows h/6 [1 4 1] (h/6 [2 1] and h/6 [1 2] at the two ends).
+__global__ void k_theta_hist(Geo G, const double2* __restrict__ Un,
+                             const double2* __restrict__ Unm1, double2* __restrict__ E) {
+  const double c = 1.0 - G.theta;
+  double scale = (G.h[0] / 6.0) * (G.h[1] / 6.0);
+  if (G.dim == 3) scale *= G.h[2] / 6.0;
+  const double cu = c * 0.5 * G.idt * scale;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < G.n_nodes;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long nn0 = G.nn[0], nn1 = G.nn[1];
+    const int ix = (int)(i % nn0);
+    const long long r = i / nn0;
+    const int iy = G.dim == 2 ? (int)r : (int)(r % nn1);
+    const int iz = G.dim == 2 ? 0 : (int)(r / nn1);
+    const int zlo = G.dim == 3 ? -1 : 0, zhi = G.dim == 3 ? 1 : 0;
+    double acc = 0.0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      const int jz = iz + dz;
+      if (jz < 0 || jz >= G.nn[2]) continue;
+      const double wz = G.dim == 2 ? 1.0 : (dz != 0 ? 1.0 : ((iz == 0 || iz == G.n[2]) ? 2.0 : 4.0));
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int jy = iy + dy;
+        if (jy < 0 || jy >= G.nn[1]) continue;
+        const double wy = dy != 0 ? 1.0 : ((iy == 0 || iy == G.n[1]) ? 2.0 : 4.0);
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int jx = ix + dx;
+          if (jx < 0 || jx >= G.nn[0]) continue;
+          const double wx = dx != 0 ? 1.0 : ((ix == 0 || ix == G.n[0]) ? 2.0 : 4.0);
+          const long long j = jx + nn0 * (jy + nn1 * (long long)jz);
+          acc = fma(wx * wy * wz, Un[j].x - Unm1[j].x, acc);
+        }
+      }
+    }
+    const double2 e = E[i];
+    E[i] = make_double2(c * e.x, fma(-cu, acc, c * e.y));
+  }
+}
+
 int check_vec(const void* p, const char* name) {
   if (!p) {
     set_error(std::string("null device pointer: ") + name);
@@ -93,6 +135,10 @@ int check_params(const pf_params* p) {
   if (!(p->dt > 0.0) || !(p->D > 0.0) || !(p->delta2 > 0.0) || !std::isfinite(p->eps4) ||
       !std::isfinite(p->lambda)) {
     set_error("dt, D, delta2 must be > 0 and eps4, lambda finite");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!(p->theta > 0.0 && p->theta <= 1.0)) {
+    set_error("theta must be in (0, 1]");
     return PF_ERR_INVALID_ARG;
   }
   return PF_OK;
@@ -308,8 +354,49 @@ void stats_reset(pf_solver_stats* st) {
   if (st) std::memset(st, 0, sizeof(*st));
 }
 
-int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_opts& o,
-                pf_solver_stats* st, hipStream_t s) {
+int ensure_load_vec(pf_problem* pb) {
+  if (pb->load_vec) return PF_OK;
+  if (hipMalloc(&pb->load_vec, pb->n_dof * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    pb->load_vec = nullptr;
+    set_error("out of device memory for the theta-step workspace");
+    return PF_ERR_OOM;
+  }
+  return PF_OK;
+}
+
+// Explicit part of a theta step (see k_theta_hist): the theta = 1 residual at
+// (U^n; U^n) -- whose time terms vanish -- is the spatial operator at U^n.
+int theta_explicit_impl(pf_problem* pb, const double* Un, const double* Unm1, double* E,
+                        hipStream_t s) {
+  const long long n = pb->n_dof;
+  if (pb->params.theta == 1.0) {
+    PF_HIP_CHECK(hipMemsetAsync(E, 0, n * sizeof(double), s));
+    return PF_OK;
+  }
+  const Geo saved = pb->geo;
+  Geo g1 = saved;
+  g1.theta = 1.0;
+  g1.idtm = g1.idt;
+  g1.Dth = g1.D;
+  g1.hth = 0.5;
+  pb->geo = g1;  // kernel arguments are captured at launch
+  const int rc = launch_residual_family(pb, MODE_RES, Un, Un, nullptr, nullptr, nullptr, E,
+                                        nullptr, nullptr, s);
+  pb->geo = saved;
+  PF_TRY(rc);
+  const long long nb = std::min<long long>((pb->geo.n_nodes + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_theta_hist, dim3((unsigned)nb), dim3(256), 0, s, pb->geo,
+                     reinterpret_cast<const double2*>(Un), reinterpret_cast<const double2*>(Unm1),
+                     reinterpret_cast<double2*>(E));
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+// Newton-Krylov for F(U; Uprev) + load = 0 (load may be NULL).  The FD
+// products use F(U; Uprev) itself as their base value: the load cancels.
+int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double* U,
+                const pf_solver_opts& o, pf_solver_stats* st, hipStream_t s) {
   const long long n = pb->n_dof;
   double* F = pb->tmp_vec[0];
   double* dU = pb->tmp_vec[1];
@@ -319,10 +406,16 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
   double* B = pb->tmp_vec[5];
   (void)rhs;
   double* coef = pc_coef_buffer(pb);
+  // |X + load|, staged through B (free outside the linear solve)
+  auto norm_loaded = [&](const double* X, double* out) -> int {
+    if (!load) return norm2(pb, X, out, s);
+    PF_TRY(blas_axpby(1.0, X, 1.0, load, B, n, s));
+    return norm2(pb, B, out, s);
+  };
   PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
                                 nullptr, s, coef));
   double f;
-  PF_TRY(norm2(pb, F, &f, s));
+  PF_TRY(norm_loaded(F, &f));
   if (!std::isfinite(f)) {
     set_error("non-finite initial residual norm");
     if (st) st->status = PF_ERR_NONFINITE;
@@ -346,7 +439,8 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
     }
     // the cell coefficients of the preconditioner came with the residual at U
     PF_TRY(pc_setup_prepared(pb, o.pc, o.pc_precision, s));
-    PF_TRY(blas_axpby(-1.0, F, 0.0, F, B, n, s));
+    if (load) PF_TRY(blas_axpby(-1.0, F, -1.0, load, B, n, s));
+    else PF_TRY(blas_axpby(-1.0, F, 0.0, F, B, n, s));
     Op op{pb, U, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
     PF_TRY(op.prepare(s));
     int its = 0;
@@ -366,7 +460,7 @@ int newton_impl(pf_problem* pb, const double* Uprev, double* U, const pf_solver_
       PF_TRY(blas_axpby(1.0, U, lam, dU, Ut, n, s));
       PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr,
                                     nullptr, s, coef));
-      PF_TRY(norm2(pb, Ft, &ft, s));
+      PF_TRY(norm_loaded(Ft, &ft));
       if (std::isfinite(ft) && ft <= f) {
         ok = true;
         break;
@@ -443,6 +537,10 @@ Geo make_geo(const pf_params& p) {
   G.a0 = 1.0 - 3.0 * p.eps4;
   G.e4x4 = 4.0 * p.eps4;
   G.e16 = 16.0 * p.eps4;
+  G.theta = p.theta;
+  G.idtm = 1.0 / (p.theta * p.dt);
+  G.Dth = p.theta * p.D;
+  G.hth = 0.5 * p.theta;
   return G;
 }
 
@@ -544,10 +642,10 @@ int pf_destroy(pf_problem* pb) {
   chk(hipDeviceSynchronize(), "hipDeviceSynchronize");
   chk(pc_free(pb), "preconditioner buffers");
   double* bufs[] = {pb->red_partials, pb->red_out, pb->elem_buf, pb->vjp_partials, pb->eps_dev,
-                    pb->V, pb->Z, pb->side_buf};
+                    pb->V, pb->Z, pb->side_buf, pb->load_vec};
   const char* names[] = {"red_partials", "red_out", "elem_buf", "vjp_partials", "eps_dev", "V", "Z",
-                         "side_buf"};
-  for (int i = 0; i < 8; ++i)
+                         "side_buf", "load_vec"};
+  for (int i = 0; i < 9; ++i)
     if (bufs[i]) chk(hipFree(bufs[i]), names[i]);
   for (int i = 0; i < kNumTmp; ++i)
     if (pb->tmp_vec[i]) chk(hipFree(pb->tmp_vec[i]), "tmp_vec");
@@ -711,12 +809,54 @@ int pf_newton_step(pf_problem* pb, const double* Uprev, double* U, const pf_solv
   PF_TRY(check_vec(U, "U"));
   stats_reset(stats);
   const double t0 = now_ms();
-  int rc = newton_impl(pb, Uprev, U, *opts, stats, S(stream));
+  int rc = newton_impl(pb, Uprev, nullptr, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;
     stats->t_total_ms = now_ms() - t0;
   }
   return rc;
+}
+
+int pf_newton_step_theta(pf_problem* pb, const double* Uprev2, const double* Uprev, double* U,
+                         const pf_solver_opts* opts, pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(U, "U"));
+  const bool weighted = pb->params.theta != 1.0;
+  if (weighted) {
+    PF_TRY(check_vec(Uprev2, "Uprev2"));
+    PF_TRY(ensure_load_vec(pb));
+  }
+  stats_reset(stats);
+  const double t0 = now_ms();
+  hipStream_t s = S(stream);
+  int rc = PF_OK;
+  if (weighted) rc = theta_explicit_impl(pb, Uprev, Uprev2, pb->load_vec, s);
+  if (rc == PF_OK)
+    rc = newton_impl(pb, Uprev, weighted ? pb->load_vec : nullptr, U, *opts, stats, s);
+  if (stats) {
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int pf_theta_explicit(pf_problem* pb, const double* Uprev, const double* Uprev2, double* E,
+                      void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(E, "E"));
+  return theta_explicit_impl(pb, Uprev, Uprev2, E, S(stream));
 }
 
 int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
@@ -737,13 +877,17 @@ int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* o
   pf_solver_stats acc;
   stats_reset(&acc);
   const double t0 = now_ms();
+  const bool weighted = pb->params.theta != 1.0;
+  if (weighted) PF_TRY(ensure_load_vec(pb));
   for (int k = 0; k < steps; ++k) {
     double* prev = states + (long long)k * n;
     double* next = prev + n;
+    const double* prev2 = k > 0 ? prev - n : prev;  // U^(-1) = U^0
+    if (weighted) PF_TRY(theta_explicit_impl(pb, prev, prev2, pb->load_vec, s));
     PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     pf_solver_stats st;
     stats_reset(&st);
-    int rc = newton_impl(pb, prev, next, *opts, &st, s);
+    int rc = newton_impl(pb, prev, weighted ? pb->load_vec : nullptr, next, *opts, &st, s);
     acc.newton_its += st.newton_its;
     acc.gmres_its_total += st.gmres_its_total;
     acc.backtracks += st.backtracks;
@@ -770,6 +914,10 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
     return PF_ERR_INVALID_ARG;
   }
   PF_TRY(check_opts(pb, opts));
+  if (pb->params.theta != 1.0) {
+    set_error("pf_adjoint_step covers backward Euler (theta = 1) only");
+    return PF_ERR_INVALID_ARG;
+  }
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(mu, "mu"));

@@ -433,7 +433,7 @@ struct PhysJvp {
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;  // dR/dphi
     const double Ru = -G.lam * om * om;                              // dR/du
-    s[0] = (2.0 * A.a * dav * dphi + A.a2 * tp) * G.idt - (Rp * tp + Ru * tu);
+    s[0] = (2.0 * A.a * dav * dphi + A.a2 * tp) * G.idtm - (Rp * tp + Ru * tu);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hv[k] : 0.0;
   }
@@ -466,10 +466,10 @@ struct PhysVjp {
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
-    const double m = 2.0 * A.a * dphi * G.idt * w1;  // d(a^2 dphi/dt w1)/da
-    s[0] = w1 * (A.a2 * G.idt - Rp);
+    const double m = 2.0 * A.a * dphi * G.idtm * w1;  // d(a^2 dphi idtm w1)/da
+    s[0] = w1 * (A.a2 * G.idtm - Rp);
     p[0] = w1 * G.lam * om * om;
-    p[1] = -w1 * A.a2 * G.idt;
+    p[1] = -w1 * A.a2 * G.idtm;
     // parameter derivatives: da/deps4 = -3 + 4 S/Q^2, d(da/dg)/deps4 = (da/dg)/eps4
     const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
     double Je_w = 0.0;
@@ -509,8 +509,8 @@ struct PhysVjpU {
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
-    const double m = 2.0 * A.a * dphi * G.idt * w1;
-    s[0] = w1 * (A.a2 * G.idt - Rp);
+    const double m = 2.0 * A.a * dphi * G.idtm * w1;
+    s[0] = w1 * (A.a2 * G.idtm - Rp);
     p[0] = w1 * G.lam * om * om;
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m, A.dadg(gg[0], k, G), Hw[k]) : 0.0;
@@ -556,30 +556,32 @@ struct Element {
     for (int a = 0; a < NA; ++a) dphi[a] = u0[a] - p0[a];
     double dummy[1][NA];
     if constexpr (MODE == MODE_RES || MODE == MODE_FD) {
-      // F2 = M (du - dphi/2)/dt + D K u
+      // F2 = M (du - theta dphi/2)/dt + theta D K u
       double y[NA];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) y[a] = (u1[a] - p1[a]) - 0.5 * dphi[a];
-      lin(G, y, G.idt, u1, G.D, out[1]);
+      for (int a = 0; a < NA; ++a) y[a] = (u1[a] - p1[a]) - G.hth * dphi[a];
+      lin(G, y, G.idt, u1, G.Dth, out[1]);
+      // F1 = theta [a^2 dphi/(theta dt) - R + J]: the Gauss rule sees the time
+      // term over theta and the element vector is scaled once
       double ngv[1][NA], nvv[2][NA], os[1][NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         ngv[0][a] = u0[a];
         nvv[0][a] = u1[a];
-        nvv[1][a] = dphi[a] * G.idt;
+        nvv[1][a] = dphi[a] * G.idtm;
         os[0][a] = 0.0;
       }
       PhysResidual<DIM> ph(G);
       quad<1, 2, 1, 0>(G, ngv, nvv, os, dummy, ph);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+      for (int a = 0; a < NA; ++a) out[0][a] = G.theta * os[0][a];
       ge = ph.ca;  // cell integral of a^2 (the cell mean times the cell volume)
     } else if constexpr (MODE == MODE_JVP) {
-      // d F2 = M (v_u - v_phi/2)/dt + D K v_u
+      // d F2 = M (v_u - theta v_phi/2)/dt + theta D K v_u
       double y[NA];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) y[a] = v1[a] - 0.5 * v0[a];
-      lin(G, y, G.idt, v1, G.D, out[1]);
+      for (int a = 0; a < NA; ++a) y[a] = v1[a] - G.hth * v0[a];
+      lin(G, y, G.idt, v1, G.Dth, out[1]);
       double ngv[2][NA], nvv[3][NA], os[1][NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
@@ -593,7 +595,7 @@ struct Element {
       PhysJvp<DIM> ph(G);
       quad<2, 3, 1, 0>(G, ngv, nvv, os, dummy, ph);
 #pragma unroll
-      for (int a = 0; a < NA; ++a) out[0][a] = os[0][a];
+      for (int a = 0; a < NA; ++a) out[0][a] = G.theta * os[0][a];
     } else if constexpr (MODE == MODE_VJPU) {
       double ngv[2][NA], nvv[2][NA], os[1][NA], op[1][NA];
 #pragma unroll
@@ -607,27 +609,28 @@ struct Element {
       }
       PhysVjpU<DIM> ph(G);
       quad<2, 2, 1, 1>(G, ngv, nvv, os, op, ph);
-      // F2 part: gU_phi -= M w2/(2dt), gU_u += M w2/dt + D K w2
+      // F2 part: gU_phi -= theta M w2/(2dt), gU_u += M w2/dt + theta D K w2
       double y[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         y[a] = G.idt * v1[a];
-        out[0][a] = os[0][a];
-        out[1][a] = op[0][a];
+        out[0][a] = G.theta * os[0][a];
+        out[1][a] = G.theta * op[0][a];
       }
-      lin(G, y, 1.0, v1, G.D, out[1]);
+      lin(G, y, 1.0, v1, G.Dth, out[1]);
       double zero[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) zero[a] = 0.0;
-      lin(G, y, -0.5, zero, 0.0, out[0]);
+      lin(G, y, -G.hth, zero, 0.0, out[0]);
     } else {
-      // F2 part of the adjoint (M, K symmetric): gU_phi -= M w2/(2dt),
-      // gU_u += M w2/dt + D K w2, gUprev_phi += M w2/(2dt), gUprev_u -= M w2/dt
+      // F2 part of the adjoint (M, K symmetric): gU_phi -= theta M w2/(2dt),
+      // gU_u += M w2/dt + theta D K w2, gUprev_phi += theta M w2/(2dt),
+      // gUprev_u -= M w2/dt
       double zero[NA], mw[NA], kw[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) zero[a] = mw[a] = kw[a] = 0.0;
       lin(G, v1, 1.0, zero, 0.0, mw);
-      lin(G, zero, 0.0, v1, G.D, kw);
+      lin(G, zero, 0.0, v1, G.Dth, kw);
       double ngv[2][NA], nvv[2][NA], os[1][NA], op[2][NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
@@ -641,13 +644,13 @@ struct Element {
       quad<2, 2, 1, 2>(G, ngv, nvv, os, op, ph);
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        out[0][a] = os[0][a] - 0.5 * G.idt * mw[a];
-        out[1][a] = op[0][a] + G.idt * mw[a] + kw[a];
-        out[2][a] = op[1][a] + 0.5 * G.idt * mw[a];
+        out[0][a] = G.theta * os[0][a] - G.hth * G.idt * mw[a];
+        out[1][a] = G.theta * op[0][a] + G.idt * mw[a] + kw[a];
+        out[2][a] = G.theta * op[1][a] + G.hth * G.idt * mw[a];
         out[3][a] = -G.idt * mw[a];
       }
-      ge = ph.ge;
-      gl = ph.gl;
+      ge = G.theta * ph.ge;
+      gl = G.theta * ph.gl;
     }
   }
 };

@@ -1,8 +1,8 @@
 // Preconditioner of the Newton-Krylov solver: M = diag(M11, M22) (the block
 // Jacobi operator of the paper's Sec. 2.3.2, Eq. pre), each block of the form
 //   A = sum_e c_e (sm M_e + sk K_e)
-// with c_e the cell mean of a(grad phi)^2 for M11 (sm = 1/dt, sk = 1) and
-// c_e = 1 for M22 (sm = 1/dt, sk = D) (Eqs. m11/pref2 and m22/preconc2 with
+// with c_e the cell mean of a(grad phi)^2 for M11 (sm = 1/dt, sk = theta) and
+// c_e = 1 for M22 (sm = 1/dt, sk = theta D) (Eqs. m11/pref2 and m22/preconc2 with
 // k = 1).  Two inverses:
 //   Jacobi  z = diag(A)^-1 r                                    (FP64)
 //   GMG     one V-cycle per block, FP32 or FP64 arithmetic:
@@ -835,7 +835,7 @@ hipError_t hier_free(Hier<T>& H) {
 template <int DIM, class T>
 int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) {
   const double sm[2] = {1.0 / pb->params.dt, 1.0 / pb->params.dt};
-  const double sk[2] = {1.0, pb->params.D};
+  const double sk[2] = {pb->params.theta, pb->params.theta * pb->params.D};
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level<T>& L = H.lv[l];
     for (int f = 0; f < 2; ++f) {
@@ -1071,8 +1071,8 @@ int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s) {
       return PF_OK;
     case PF_PC_JACOBI: {
       double Ae0[8], Ae1[8];
-      element_table(G.dim, G.h, 1.0 / pb->params.dt, 1.0, Ae0);
-      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.D, Ae1);
+      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.theta, Ae0);
+      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.theta * pb->params.D, Ae1);
       hipLaunchKernelGGL(k_jacobi, dim3(blocks(n)), dim3(kT), 0, s, G, (const double*)st->coef0,
                          reinterpret_cast<const double2*>(r), reinterpret_cast<double2*>(z),
                          Ae0[0], Ae1[0]);

@@ -44,6 +44,9 @@ struct Geo {
   double jac;    // prod(h/2): Jacobian of the reference map
   double dt, idt, eps4, lam, D, delta2;
   double a0, e4x4, e16;  // 1 - 3 eps4, 4 eps4, 16 eps4
+  // time weight: the phi-row terms are theta * [a^2 dphi idtm + spatial],
+  // idtm = 1/(theta dt); Dth = theta D, hth = theta/2 (latent rate)
+  double theta, idtm, Dth, hth;
 };
 
 Geo make_geo(const pf_params& p);
@@ -126,9 +129,9 @@ struct pf_problem {
 
   // reduction scratch: partial sums [k][n_red_blocks] and results
   int n_red_blocks;
-  double* red_partials;  // (32 + 2) * n_red_blocks
-  double* red_out;       // 256 doubles of device results
-  double* host_pinned;   // 256 doubles of pinned host staging
+  double* red_partials;  // 64 * n_red_blocks
+  double* red_out;       // 512 doubles of device results
+  double* host_pinned;   // 512 doubles of pinned host staging
 
   // residual-family scratch
   double* elem_buf;      // element contributions (element pass)
@@ -139,6 +142,7 @@ struct pf_problem {
   int n_elem_blocks;
   double* eps_dev;       // FD epsilon (device scalar)
   double* tmp_vec[6];    // work vectors of n_dof doubles (kNumTmp)
+  double* load_vec;      // theta < 1: the explicit part E of the step (lazy)
 
   // FGMRES basis
   double* V;  // (m+1) * n_dof

@@ -27,8 +27,10 @@ class PhaseFieldEvolve(torch.autograd.Function):
                 problem: binding.Problem, steps: int, opts: Optional[binding.pf_solver_opts] = None):
         o = opts if opts is not None else binding.default_opts()
         p = problem.params
+        if p.theta != 1.0:
+            raise ValueError("the adjoint covers backward Euler (theta = 1) only")
         params = binding.make_params(p.dim, list(p.n)[:p.dim], list(p.half_width)[:p.dim], p.dt,
-                                     float(eps4), float(lam), p.D, p.delta2)
+                                     float(eps4), float(lam), p.D, p.delta2, p.theta)
         problem.set_params(params)
         n = problem.n_dof
         states = torch.empty((steps + 1) * n, dtype=torch.float64, device=U0.device)

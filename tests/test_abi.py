@@ -43,7 +43,7 @@ def test_ctypes_structs_match_c_layout(tmp_path):
 #include <stddef.h>
 #include "pfjfnk.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\\n", sizeof(pf_params), offsetof(pf_params, dt), offsetof(pf_params, delta2), offsetof(pf_params, half_width));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(pf_params), offsetof(pf_params, dt), offsetof(pf_params, delta2), offsetof(pf_params, half_width), offsetof(pf_params, theta));
   printf("%zu %zu %zu\\n", sizeof(pf_solver_opts), offsetof(pf_solver_opts, eta0), offsetof(pf_solver_opts, pc_precision));
   printf("%zu %zu %zu\\n", sizeof(pf_solver_stats), offsetof(pf_solver_stats, fnorm), offsetof(pf_solver_stats, t_total_ms));
   return 0;
@@ -53,7 +53,7 @@ int main(void) {
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P, O, S = binding.pf_params, binding.pf_solver_opts, binding.pf_solver_stats
-    expect = [ctypes.sizeof(P), P.dt.offset, P.delta2.offset, P.half_width.offset,
+    expect = [ctypes.sizeof(P), P.dt.offset, P.delta2.offset, P.half_width.offset, P.theta.offset,
               ctypes.sizeof(O), O.eta0.offset, O.pc_precision.offset,
               ctypes.sizeof(S), S.fnorm.offset, S.t_total_ms.offset]
     assert [int(v) for v in out] == expect
@@ -72,6 +72,10 @@ def test_host_side_argument_validation_without_gpu():
     assert lib.pf_create(ctypes.byref(bad), 30, ctypes.byref(h)) == binding.PF_ERR_INVALID_ARG
     bad = binding.make_params(2, [8, 8], [1.0, 1.0], -0.1, 0.02, 1.6, 2.0)
     assert lib.pf_create(ctypes.byref(bad), 30, ctypes.byref(h)) == binding.PF_ERR_INVALID_ARG
+    for th in (0.0, -0.5, 1.5, float("nan")):
+        bad = binding.make_params(2, [8, 8], [1.0, 1.0], 0.1, 0.02, 1.6, 2.0, theta=th)
+        assert lib.pf_create(ctypes.byref(bad), 30, ctypes.byref(h)) == binding.PF_ERR_INVALID_ARG
+        assert b"theta" in lib.pf_last_error()
     good = binding.make_params(2, [8, 8], [1.0, 1.0], 0.1, 0.02, 1.6, 2.0)
     assert lib.pf_create(ctypes.byref(good), 0, ctypes.byref(h)) == binding.PF_ERR_INVALID_ARG
     assert lib.pf_residual(None, None, None, None, None) == binding.PF_ERR_INVALID_ARG
