@@ -17,7 +17,8 @@ region: (number of Jv and VJP applications performed, inside and outside the
 Krylov solves) x unknowns / timed wall time, in MDOF/s.  The roofline object
 is for the element kernel of the residual family, timed live with HIP events
 on its stream.  After the timed region the same Newton step is repeated from
-the same state with the FP64 V-cycle for the mixed-vs-FP64 comparison, and the
+the same state with the FP64 V-cycle for the mixed-vs-FP64 comparison, one
+Crank-Nicolson (theta = 1/2) step continues from the last two states, and the
 CPU oracle is timed on a bounded slab of the same workload.
 """
 from __future__ import annotations
@@ -50,22 +51,24 @@ def flops_per_element(dim):
 
     Linear part (u equation, latent heat) by exact tensor-product element
     matrices; Gauss part for the phi equation with phi interpolated with its
-    gradient, u and (phi - phi^n)/dt as values, one output with value and flux
-    parts; pointwise physics 52 flops in 3-D (40 in 2-D) including a
-    reciprocal with two Newton steps and the a^2 accumulation for the
-    preconditioner coefficient.
+    gradient, u and (phi - phi^n)/(theta dt) as values, one output with value
+    and flux parts, point sums taken with the x weights only and scaled per
+    row.  Pointwise physics 52 flops in 3-D (40 in 2-D) including a reciprocal
+    with two Newton steps and the a^2 accumulation for the preconditioner
+    coefficient.  Interpolation uses q0 + b1 (q1 - q0), so each point costs one
+    FMA per interpolated value.
     3-D: corner differences and scalings 48 + linear part 264 + 3 planes x
-    (interpolation 44 + contraction 32) + 9 rows x (interpolation 28 +
-    weights 2 + contraction 28) + 27 points x (interpolation 17 + physics 52
-    + weights 3 + contraction 14) = 3384.
+    (interpolation 40 + contraction 32) + 9 rows x (interpolation 26 + x
+    differences 6 + weights 5 + contraction 30) + 27 points x (interpolation 10
+    + physics 52 + contraction 14) = 3183.
     2-D: corner differences and scalings 24 + linear part 88 + 3 rows x
-    (interpolation 14 + contraction 20) + 9 points x (interpolation 12 +
-    physics 40 + weights 3 + contraction 10) = 799.
+    (interpolation 20 + x differences 5 + weights 4 + contraction 22) + 9 points
+    x (interpolation 8 + physics 40 + contraction 10) = 787.
     The scalings include the time weight theta applied to the element vector.
     """
     if dim == 3:
-        return 48 + 264 + 3 * (44 + 32) + 9 * (28 + 2 + 28) + 27 * (17 + 52 + 3 + 14)
-    return 24 + 88 + 3 * (14 + 20) + 9 * (12 + 40 + 3 + 10)
+        return 48 + 264 + 3 * (40 + 32) + 9 * (26 + 6 + 5 + 30) + 27 * (10 + 52 + 14)
+    return 24 + 88 + 3 * (20 + 5 + 4 + 22) + 9 * (8 + 40 + 10)
 
 
 FLOPS_PER_ELEM = {3: flops_per_element(3), 2: flops_per_element(2)}
@@ -217,6 +220,24 @@ def main():
         cmp["speedup_mixed"] = round(res["fp64_gmg"][0] / res["fp32_gmg"][0], 3)
         log("fp64 comparison done")
 
+    # ---- one Crank-Nicolson (theta = 1/2) step continuing from the last state,
+    # with the last two states as U^n and U^(n-1)
+    cn = None
+    if not a.no_fp64_compare:
+        p = pb.params
+        half = binding.make_params(p.dim, list(p.n)[:p.dim], list(p.half_width)[:p.dim], p.dt, p.eps4,
+                                   p.lambda_, p.D, p.delta2, theta=0.5)
+        pb.set_params(half)
+        Ux = U.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = pb.pf_newton_step_theta(Uprev, U, Ux, opts)
+        torch.cuda.synchronize()
+        cn = {"ms": round(1e3 * (time.perf_counter() - t1), 2), "newton_its": st["newton_its"],
+              "gmres_its": st["gmres_its_total"], "f_final_rel": st["f_final"] / st["f0"]}
+        pb.set_params(p)
+        log("theta = 1/2 step done")
+
     # ---- CPU oracle on a bounded slab of the same workload
     cpu = None
     if not a.no_cpu_baseline:
@@ -251,6 +272,7 @@ def main():
                    for s in newton],
         "adjoint": [{"gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)} for s in adj],
         "mixed_vs_fp64": cmp,
+        "theta_half_step": cn,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

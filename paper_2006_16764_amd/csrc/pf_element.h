@@ -44,6 +44,9 @@ struct Q1 {
     return g == 0 ? 0.5 * (1.0 - s) : (g == 1 ? 0.5 : 0.5 * (1.0 + s));
   }
   __host__ __device__ static constexpr double w(int g) { return g == 1 ? 8.0 / 9.0 : 5.0 / 9.0; }
+  // w(g) b0(g) and w(g) b1(g): the point weights of the two test-function halves
+  __host__ __device__ static constexpr double c0(int g) { return w(g) * b0(g); }
+  __host__ __device__ static constexpr double c1(int g) { return w(g) * b1(g); }
 };
 
 // ----------------------------------------------------------------- exact linear part
@@ -109,8 +112,11 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // ----------------------------------------------------------------- Gauss-rule part, 3-D
 // NG fields interpolated with value and gradient (ng), NV fields with value
 // only (nv); NS outputs with value and flux parts (os), NP value-only outputs
-// (op).  The functor is called as phys(gv, gg, vv, s, f, p) at every point and
-// phys.weight(w_q) right after.
+// (op).  The functor is called as phys(gv, gg, vv, s, f, p) at every point,
+// phys.weight(w_x) right after with the point's x weight, and phys.row(w_row)
+// at the end of each row of points with the row's weight (y, z weights and
+// the Jacobian): point weight = w_x w_row.  Row sums are accumulated with the
+// x weights only and scaled once per row.
 template <int NG, int NV, int NS, int NP, class Phys>
 __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
                                      const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS][8],
@@ -120,17 +126,20 @@ __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
   for (int gz = 0; gz < 3; ++gz) {
     const double bz0 = Q1::b0(gz), bz1 = Q1::b1(gz);
     double pg[NG][4], dz[NG][4], pv[NV > 0 ? NV : 1][4];
+    // b0 + b1 = 1: value = q0 + b1 (q1 - q0), and the difference also gives
+    // the derivative along the axis
 #pragma unroll
     for (int f = 0; f < NG; ++f)
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        pg[f][a] = bz0 * ng[f][a] + bz1 * ng[f][a + 4];
-        dz[f][a] = (ng[f][a + 4] - ng[f][a]) * ihz;
+        const double d = ng[f][a + 4] - ng[f][a];
+        pg[f][a] = fma(bz1, d, ng[f][a]);
+        dz[f][a] = d * ihz;
       }
 #pragma unroll
     for (int f = 0; f < NV; ++f)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) pv[f][a] = bz0 * nv[f][a] + bz1 * nv[f][a + 4];
+      for (int a = 0; a < 4; ++a) pv[f][a] = fma(bz1, nv[f][a + 4] - nv[f][a], nv[f][a]);
     double S[NS][4], Zc[NS][4], P[NP > 0 ? NP : 1][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -143,18 +152,32 @@ PF_UNROLL(PF_GY_UNROLL)
     for (int gy = 0; gy < 3; ++gy) {
       const double by0 = Q1::b0(gy), by1 = Q1::b1(gy);
       const double wrow = Q1::w(gy) * Q1::w(gz) * G.jac;
+      const double wb0 = wrow * by0, wb1 = wrow * by1, wih = wrow * ihy;
       double qv[NG][2], qy[NG][2], qz[NG][2], qw[NV > 0 ? NV : 1][2];
 #pragma unroll
       for (int ax = 0; ax < 2; ++ax) {
 #pragma unroll
         for (int f = 0; f < NG; ++f) {
-          qv[f][ax] = by0 * pg[f][ax] + by1 * pg[f][ax + 2];
-          qy[f][ax] = (pg[f][ax + 2] - pg[f][ax]) * ihy;
-          qz[f][ax] = by0 * dz[f][ax] + by1 * dz[f][ax + 2];
+          const double d = pg[f][ax + 2] - pg[f][ax];
+          qv[f][ax] = fma(by1, d, pg[f][ax]);
+          qy[f][ax] = d * ihy;
+          qz[f][ax] = fma(by1, dz[f][ax + 2] - dz[f][ax], dz[f][ax]);
         }
 #pragma unroll
-        for (int f = 0; f < NV; ++f) qw[f][ax] = by0 * pv[f][ax] + by1 * pv[f][ax + 2];
+        for (int f = 0; f < NV; ++f) qw[f][ax] = fma(by1, pv[f][ax + 2] - pv[f][ax], pv[f][ax]);
       }
+      // differences along x, shared by the row's three points; the x
+      // derivative is constant along a row of a Q1 element
+      double dqv[NG], gxr[NG], dqy[NG], dqz[NG], dqw[NV > 0 ? NV : 1];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        dqv[f] = qv[f][1] - qv[f][0];
+        gxr[f] = dqv[f] * ihx;
+        dqy[f] = qy[f][1] - qy[f][0];
+        dqz[f] = qz[f][1] - qz[f][0];
+      }
+#pragma unroll
+      for (int f = 0; f < NV; ++f) dqw[f] = qw[f][1] - qw[f][0];
       double rs[NS][2], rx[NS], ry[NS][2], rz[NS][2], rp[NP > 0 ? NP : 1][2];
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
@@ -164,21 +187,20 @@ PF_UNROLL(PF_GY_UNROLL)
 #pragma unroll
       for (int o = 0; o < NP; ++o) rp[o][0] = rp[o][1] = 0.0;
       auto point = [&](int gx) {
-        const double bx0 = Q1::b0(gx), bx1 = Q1::b1(gx);
+        const double bx1 = Q1::b1(gx);
         double gv[NG], gg[NG][3], vv[NV > 0 ? NV : 1];
 #pragma unroll
         for (int f = 0; f < NG; ++f) {
-          gv[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
-          gg[f][0] = (qv[f][1] - qv[f][0]) * ihx;
-          gg[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
-          gg[f][2] = bx0 * qz[f][0] + bx1 * qz[f][1];
+          gv[f] = fma(bx1, dqv[f], qv[f][0]);
+          gg[f][0] = gxr[f];
+          gg[f][1] = fma(bx1, dqy[f], qy[f][0]);
+          gg[f][2] = fma(bx1, dqz[f], qz[f][0]);
         }
 #pragma unroll
-        for (int f = 0; f < NV; ++f) vv[f] = bx0 * qw[f][0] + bx1 * qw[f][1];
+        for (int f = 0; f < NV; ++f) vv[f] = fma(bx1, dqw[f], qw[f][0]);
         double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
         phys(gv, gg, vv, s, fl, p);
-        const double wq = Q1::w(gx) * wrow;
-        const double w0 = wq * bx0, w1 = wq * bx1;
+        const double wq = Q1::w(gx), w0 = Q1::c0(gx), w1 = Q1::c1(gx);
         phys.weight(wq);
 #pragma unroll
         for (int o = 0; o < NS; ++o) {
@@ -203,25 +225,26 @@ PF_UNROLL(PF_GY_UNROLL)
 #pragma unroll
         for (int gx = 0; gx < 3; ++gx) point(gx);
       }
+      phys.row(wrow);
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
         const double sx0 = rs[o][0] - rx[o] * ihx;
         const double sx1 = rs[o][1] + rx[o] * ihx;
-        S[o][0] += by0 * sx0 - ry[o][0] * ihy;
-        S[o][1] += by0 * sx1 - ry[o][1] * ihy;
-        S[o][2] += by1 * sx0 + ry[o][0] * ihy;
-        S[o][3] += by1 * sx1 + ry[o][1] * ihy;
-        Zc[o][0] += by0 * rz[o][0];
-        Zc[o][1] += by0 * rz[o][1];
-        Zc[o][2] += by1 * rz[o][0];
-        Zc[o][3] += by1 * rz[o][1];
+        S[o][0] += wb0 * sx0 - ry[o][0] * wih;
+        S[o][1] += wb0 * sx1 - ry[o][1] * wih;
+        S[o][2] += wb1 * sx0 + ry[o][0] * wih;
+        S[o][3] += wb1 * sx1 + ry[o][1] * wih;
+        Zc[o][0] += wb0 * rz[o][0];
+        Zc[o][1] += wb0 * rz[o][1];
+        Zc[o][2] += wb1 * rz[o][0];
+        Zc[o][3] += wb1 * rz[o][1];
       }
 #pragma unroll
       for (int o = 0; o < NP; ++o) {
-        P[o][0] += by0 * rp[o][0];
-        P[o][1] += by0 * rp[o][1];
-        P[o][2] += by1 * rp[o][0];
-        P[o][3] += by1 * rp[o][1];
+        P[o][0] += wb0 * rp[o][0];
+        P[o][1] += wb0 * rp[o][1];
+        P[o][2] += wb1 * rp[o][0];
+        P[o][3] += wb1 * rp[o][1];
       }
     }
 #pragma unroll
@@ -249,17 +272,29 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
 #pragma unroll
   for (int gy = 0; gy < 3; ++gy) {
     const double by0 = Q1::b0(gy), by1 = Q1::b1(gy);
+    const double wrow = Q1::w(gy) * G.jac;
+    const double wb0 = wrow * by0, wb1 = wrow * by1, wih = wrow * ihy;
     double qv[NG][2], qy[NG][2], qw[NV > 0 ? NV : 1][2];
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
-        qv[f][ax] = by0 * ng[f][ax] + by1 * ng[f][ax + 2];
-        qy[f][ax] = (ng[f][ax + 2] - ng[f][ax]) * ihy;
+        const double d = ng[f][ax + 2] - ng[f][ax];
+        qv[f][ax] = fma(by1, d, ng[f][ax]);
+        qy[f][ax] = d * ihy;
       }
 #pragma unroll
-      for (int f = 0; f < NV; ++f) qw[f][ax] = by0 * nv[f][ax] + by1 * nv[f][ax + 2];
+      for (int f = 0; f < NV; ++f) qw[f][ax] = fma(by1, nv[f][ax + 2] - nv[f][ax], nv[f][ax]);
     }
+    double dqv[NG], gxr[NG], dqy[NG], dqw[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      dqv[f] = qv[f][1] - qv[f][0];
+      gxr[f] = dqv[f] * ihx;
+      dqy[f] = qy[f][1] - qy[f][0];
+    }
+#pragma unroll
+    for (int f = 0; f < NV; ++f) dqw[f] = qw[f][1] - qw[f][0];
     double rs[NS][2], rx[NS], ry[NS][2], rp[NP > 0 ? NP : 1][2];
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
@@ -270,21 +305,20 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
     for (int o = 0; o < NP; ++o) rp[o][0] = rp[o][1] = 0.0;
 #pragma unroll
     for (int gx = 0; gx < 3; ++gx) {
-      const double bx0 = Q1::b0(gx), bx1 = Q1::b1(gx);
+      const double bx1 = Q1::b1(gx);
       double gv[NG], gg[NG][3], vv[NV > 0 ? NV : 1];
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
-        gv[f] = bx0 * qv[f][0] + bx1 * qv[f][1];
-        gg[f][0] = (qv[f][1] - qv[f][0]) * ihx;
-        gg[f][1] = bx0 * qy[f][0] + bx1 * qy[f][1];
+        gv[f] = fma(bx1, dqv[f], qv[f][0]);
+        gg[f][0] = gxr[f];
+        gg[f][1] = fma(bx1, dqy[f], qy[f][0]);
         gg[f][2] = 0.0;
       }
 #pragma unroll
-      for (int f = 0; f < NV; ++f) vv[f] = bx0 * qw[f][0] + bx1 * qw[f][1];
+      for (int f = 0; f < NV; ++f) vv[f] = fma(bx1, dqw[f], qw[f][0]);
       double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
       phys(gv, gg, vv, s, fl, p);
-      const double wq = Q1::w(gx) * Q1::w(gy) * G.jac;
-      const double w0 = wq * bx0, w1 = wq * bx1;
+      const double wq = Q1::w(gx), w0 = Q1::c0(gx), w1 = Q1::c1(gx);
       phys.weight(wq);
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
@@ -300,21 +334,22 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
         rp[o][1] = fma(p[o], w1, rp[o][1]);
       }
     }
+    phys.row(wrow);
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
       const double sx0 = rs[o][0] - rx[o] * ihx;
       const double sx1 = rs[o][1] + rx[o] * ihx;
-      os[o][0] += by0 * sx0 - ry[o][0] * ihy;
-      os[o][1] += by0 * sx1 - ry[o][1] * ihy;
-      os[o][2] += by1 * sx0 + ry[o][0] * ihy;
-      os[o][3] += by1 * sx1 + ry[o][1] * ihy;
+      os[o][0] += wb0 * sx0 - ry[o][0] * wih;
+      os[o][1] += wb0 * sx1 - ry[o][1] * wih;
+      os[o][2] += wb1 * sx0 + ry[o][0] * wih;
+      os[o][3] += wb1 * sx1 + ry[o][1] * wih;
     }
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
-      op[o][0] += by0 * rp[o][0];
-      op[o][1] += by0 * rp[o][1];
-      op[o][2] += by1 * rp[o][0];
-      op[o][3] += by1 * rp[o][1];
+      op[o][0] += wb0 * rp[o][0];
+      op[o][1] += wb0 * rp[o][1];
+      op[o][2] += wb1 * rp[o][0];
+      op[o][3] += wb1 * rp[o][1];
     }
   }
 }
@@ -392,10 +427,15 @@ template <int DIM>
 struct PhysResidual {
   static constexpr int kGxUnroll = 1;
   const Geo& G;
-  double ca;  // sum of w_q a^2 over the element (preconditioner coefficient)
+  double ca;   // sum of w_q a^2 over the element (preconditioner coefficient)
+  double car;  // the current row's sum of w_x a^2
   double a2;
-  __device__ PhysResidual(const Geo& g) : G(g), ca(0.0), a2(0.0) {}
-  __device__ __forceinline__ void weight(double wq) { ca = fma(wq, a2, ca); }
+  __device__ PhysResidual(const Geo& g) : G(g), ca(0.0), car(0.0), a2(0.0) {}
+  __device__ __forceinline__ void weight(double wx) { car = fma(wx, a2, car); }
+  __device__ __forceinline__ void row(double wrow) {
+    ca = fma(wrow, car, ca);
+    car = 0.0;
+  }
   // vv[1] holds (phi - phi^n)/dt
   __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
                                              const double* vv, double* s, double (*f)[3],
@@ -420,6 +460,7 @@ struct PhysJvp {
   const Geo& G;
   __device__ PhysJvp(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}
+  __device__ __forceinline__ void row(double) {}
   __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
                                              const double* vv, double* s, double (*f)[3],
                                              double*) {
@@ -447,12 +488,19 @@ template <int DIM>
 struct PhysVjp {
   static constexpr int kGxUnroll = 3;
   const Geo& G;
-  double ge, gl;  // element accumulators
-  double pe, pl;  // pointwise values (weighted in weight())
-  __device__ PhysVjp(const Geo& g) : G(g), ge(0.0), gl(0.0), pe(0.0), pl(0.0) {}
-  __device__ __forceinline__ void weight(double wq) {
-    ge += wq * pe;
-    gl += wq * pl;
+  double ge, gl;    // element accumulators
+  double ger, glr;  // the current row's sums with the x weights
+  double pe, pl;    // pointwise values (weighted in weight())
+  __device__ PhysVjp(const Geo& g)
+      : G(g), ge(0.0), gl(0.0), ger(0.0), glr(0.0), pe(0.0), pl(0.0) {}
+  __device__ __forceinline__ void weight(double wx) {
+    ger = fma(wx, pe, ger);
+    glr = fma(wx, pl, glr);
+  }
+  __device__ __forceinline__ void row(double wrow) {
+    ge = fma(wrow, ger, ge);
+    gl = fma(wrow, glr, gl);
+    ger = glr = 0.0;
   }
   __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
                                              const double* vv, double* s, double (*f)[3],
@@ -497,6 +545,7 @@ struct PhysVjpU {
   const Geo& G;
   __device__ PhysVjpU(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}
+  __device__ __forceinline__ void row(double) {}
   __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
                                              const double* vv, double* s, double (*f)[3],
                                              double* p) {
