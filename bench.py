@@ -18,8 +18,10 @@ Krylov solves) x unknowns / timed wall time, in MDOF/s.  The roofline object
 is for the element kernel of the residual family, timed live with HIP events
 on its stream.  After the timed region the same Newton step is repeated from
 the same state with the FP64 V-cycle for the mixed-vs-FP64 comparison, one
-Crank-Nicolson (theta = 1/2) step continues from the last two states, and the
-CPU oracle is timed on a bounded slab of the same workload.
+Crank-Nicolson (theta = 1/2) step continues from the last two states, the
+CPU oracle is timed on a bounded slab of the same workload, and the alloy model
+(directional solidification, 1024 x 256 x 256 elements, theta = 1/2,
+dt = 0.002) takes a warm-up and two timed steps on its own seeded state.
 """
 from __future__ import annotations
 
@@ -43,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--alloy-workload", default="alloy3d_1024x256x256")
+    ap.add_argument("--alloy-steps", type=int, default=2)
+    ap.add_argument("--no-alloy", action="store_true")
     return ap.parse_args()
 
 
@@ -244,6 +249,14 @@ def main():
         cpu = cpu_baseline(w, U.cpu().numpy(), Uprev.cpu().numpy(), vdir.cpu().numpy(), a.cpu_seconds)
         log("cpu baseline done")
 
+    # ---- alloy model (directional solidification) on its own workload
+    alloy = None
+    if not a.no_alloy:
+        del F, Jv, gU, gP, mu, lam, mu_prev
+        pb.close()
+        torch.cuda.empty_cache()
+        alloy = alloy_leg(a, binding, inputs, torch, dev, time_call, stream)
+
     out = {
         "metric": "Jv MDOF/s + JFNK step time, mixed vs FP64 at 256^3 hex; % HBM roofline",
         "value": round(value, 2),
@@ -274,9 +287,60 @@ def main():
         "mixed_vs_fp64": cmp,
         "theta_half_step": cn,
         "cpu_baseline": cpu,
+        "alloy": alloy,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def alloy_leg(a, binding, inputs, torch, dev, time_call, stream):
+    """Theta = 1/2 steps of the alloy model (two-pass element kernels) from the
+    seeded directional-growth state; kernel timings with HIP events."""
+    w = inputs.alloy_workload(a.alloy_workload)
+    log(f"alloy workload {w.name}: n={w.n} dof={w.n_dof}")
+    pb = binding.alloy_problem_for(w, gmres_m_max=30)
+    n = pb.n_dof
+    S0 = torch.from_numpy(inputs.alloy_initial_state(w).reshape(-1)).to(dev)
+    S1, S2 = S0.clone(), pb.new_vector()
+    opts = binding.default_opts(pc=binding.PF_PC_GMG, pc_precision=binding.PF_FP32,
+                                jv_mode=binding.PF_JV_FD, tau_r=1e-10)
+    # warm-up: the first step of the run (history U^(-1) = U^0)
+    st = pb.pf_alloy_step(S0, S0, 0.0, S1, opts)
+    log(f"alloy warm-up step: newton {st['newton_its']} gmres {st['gmres_its_total']}")
+    recs = []
+    prev2, prev, t = S0, S1, w.dt
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.alloy_steps):
+        S2.copy_(prev)
+        st = pb.pf_alloy_step(prev2, prev, t, S2, opts)
+        recs.append(st)
+        prev2, prev, S2 = prev, S2, prev2
+        t += w.dt
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(a.alloy_steps, 1)
+    v = torch.from_numpy(np.random.default_rng(31).standard_normal(n)).to(dev)
+    F, J = pb.new_vector(), pb.new_vector()
+    reps = max(2, a.kernel_reps // 4)
+    t_res = time_call(lambda: pb.pf_alloy_residual(prev, prev2, prev2, t, F), reps)
+    t_fd = time_call(lambda: pb.pf_alloy_jvp(prev, prev2, prev2, t, v, J, mode=binding.PF_JV_FD, F0=F), reps)
+    t_jv = time_call(lambda: pb.pf_alloy_jvp(prev, prev2, prev2, t, v, J, mode=binding.PF_JV_ANALYTIC), reps)
+    pb.pf_precond_setup(prev, binding.PF_PC_GMG, binding.PF_FP32)
+    t_pc = time_call(lambda: pb.pf_precond_apply(v, J), reps)
+    jv = sum(r["gmres_its_total"] for r in recs)
+    out = {"workload": f"{w.name}: {w.dim}-D Q1 {'x'.join(map(str, w.n))}, h={w.h}, k={w.k}, "
+                       f"lambda={w.lam}, eps4={w.eps4}, theta={w.theta}, dt={w.dt}",
+           "unknowns": n, "steps": a.alloy_steps, "ms_per_step": round(ms, 1),
+           "jv_mdofs": round(jv * n / (ms * 1e-3 * a.alloy_steps) / 1e6, 1),
+           "newton": [{"its": r["newton_its"], "gmres": r["gmres_its_total"], "ms": round(r["t_total_ms"], 1)}
+                      for r in recs],
+           "kernels_ms": {"residual": round(t_res, 3), "fd_jv": round(t_fd, 3), "analytic_jv": round(t_jv, 3),
+                          "vcycle_fp32": round(t_pc, 3)},
+           "kernels_mdofs": {k: round(n / (x * 1e-3) / 1e6, 1) for k, x in
+                             (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv))}}
+    log("alloy leg done")
+    pb.close()
+    return out
 
 
 def cpu_baseline(w, U, Uprev, v, seconds):

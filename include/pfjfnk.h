@@ -252,6 +252,67 @@ int pf_misfit(pf_problem* pb, const double* U, const double* phi_target, double*
  * (device result).  Exposed for tests of the reduction kernels. */
 int pf_dot(pf_problem* pb, const double* x, const double* y, double* out_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Alloy model: directional solidification of a dilute binary alloy (Sec. 4.3,
+ * Eqs. pf2, lambda, directional, conc2, jat, with the weight theta of Eq.
+ * theta).  u is the non-dimensional solute field, cu = 1 + (1 - k) u, and the
+ * part of the step residual that depends on the new state U is
+ *
+ *   F1_i = (cu a^2 (phi - phi^n)/dt, psi_i) + theta (J(grad phi), grad psi_i)
+ *          - theta (phi - phi^3 - lambda (1 - phi^2)^2 (u + G4(x, t)), psi_i)
+ *   F2_i = ((1 + k)/2 (u - u^n)/dt, psi_i) + theta (D (1 - phi)/2 grad u, grad psi_i)
+ *          + (cu phihat grad phi / (2 sqrt(2) |grad phi|), grad psi_i) - (phihat cu / 2, psi_i)
+ *
+ * with phihat = theta (phi - phi^n)/dt + (1 - theta)(phi^n - phi^(n-1))/dt
+ * (Eq. theta), the frozen temperature G4(x, t) = (x - x_iso - v_pull t)/l_T
+ * (Eq. directional, x = mesh coordinate along axis 0) and |grad phi| taken as
+ * sqrt(|grad phi|^2 + delta2).  The part fixed by U^n is
+ *   E = (1 - theta) [ (J(grad phi^n), grad psi) - (G3(phi^n)(u^n + G4(x, t^n)), psi) ;
+ *                     (D (1 - phi^n)/2 grad u^n, grad psi) ].
+ * The anisotropy, dt, theta, lambda, D, delta2 come from pf_params.  The
+ * preconditioner keeps the block form of Eq. pre with the phi block
+ * (1/dt) M_c + theta K_c (c = cell mean of a^2) and the u block
+ * (1+k)/(2 dt) M + theta D K (the one-sided mobility taken as its liquid
+ * value).  A handle switched to this model accepts only the pf_alloy_* calls
+ * below, pf_precond_setup/apply, pf_misfit and pf_dot; no VJP or adjoint.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double k;      /* partition coefficient, 0 < k <= 1 */
+  double l_T;    /* thermal length in units of W0, > 0 (+inf: no gradient) */
+  double x_iso;  /* isotherm position at t = 0 (mesh coordinate along axis 0) */
+  double v_pull; /* pulling speed in units of W0/tau0 */
+} pf_alloy_params;
+
+/* Switch the handle to the alloy model (host; allocates the history field
+ * and, in 3-D, the element buffer of the two-pass element kernels:
+ * 16 * 8 bytes per element).  PF_ERR_INVALID_ARG on bad parameters,
+ * PF_ERR_OOM when the buffers do not fit. */
+int pf_set_alloy(pf_problem* pb, const pf_alloy_params* alloy);
+
+/* [async] F = implicit part of the alloy step at time t (= t^{n+1}) from
+ * Uprev = U^n and Uprev2 = U^(n-1).  All vectors: device, 2*n_nodes doubles. */
+int pf_alloy_residual(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                      double t, double* F, void* stream);
+
+/* [async] E = part of the alloy step fixed by Uprev = U^n at time t_prev = t^n. */
+int pf_alloy_explicit(pf_problem* pb, const double* Uprev, double t_prev, double* E, void* stream);
+
+/* [async] Jv of the implicit part (modes as pf_jvp: PF_JV_FD with F0 the
+ * implicit part at U, or NULL; PF_JV_ANALYTIC exact, by forward-mode
+ * differentiation of the pointwise terms). */
+int pf_alloy_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                 double t, const double* v, const double* F0, int mode, double* Jv, void* stream);
+
+/* [sync] One alloy step from t_prev: Newton-Krylov as pf_newton_step on
+ * F(U) + E = 0 starting from U_inout (usually a copy of Uprev). */
+int pf_alloy_step(pf_problem* pb, const double* Uprev2, const double* Uprev, double t_prev,
+                  double* U_inout, const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
+
+/* [sync] steps alloy steps from states[0] at time t0 (layout as pf_evolve;
+ * the first step takes U^(-1) = U^0). */
+int pf_alloy_evolve(pf_problem* pb, double* states, int steps, double t0,
+                    const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
+
 /* Thread-local message describing the last error ("" if none). */
 const char* pf_last_error(void);
 

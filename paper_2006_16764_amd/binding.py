@@ -48,6 +48,11 @@ class pf_params(ctypes.Structure):
                 ("D", ctypes.c_double), ("delta2", ctypes.c_double), ("theta", ctypes.c_double)]
 
 
+class pf_alloy_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_double), ("l_T", ctypes.c_double), ("x_iso", ctypes.c_double),
+                ("v_pull", ctypes.c_double)]
+
+
 class pf_solver_opts(ctypes.Structure):
     _fields_ = [("tau_r", ctypes.c_double), ("tau_a", ctypes.c_double),
                 ("max_newton", ctypes.c_int), ("max_backtracks", ctypes.c_int),
@@ -97,6 +102,16 @@ _SIGS = {
                                        ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_misfit": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pf_dot": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "pf_set_alloy": (ctypes.c_int, [_VP, ctypes.POINTER(pf_alloy_params)]),
+    "pf_alloy_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP]),
+    "pf_alloy_explicit": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
+    "pf_alloy_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, ctypes.c_int, _VP,
+                                    _VP]),
+    "pf_alloy_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_double, _VP, ctypes.POINTER(pf_solver_opts),
+                                     ctypes.POINTER(pf_solver_stats), _VP]),
+    "pf_alloy_evolve": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.c_double,
+                                       ctypes.POINTER(pf_solver_opts), ctypes.POINTER(pf_solver_stats),
+                                       _VP]),
     "pf_last_error": (ctypes.c_char_p, []),
 }
 
@@ -271,6 +286,43 @@ class Problem:
                                       _stream(stream)), "pf_adjoint_step")
         return st.as_dict()
 
+    def pf_set_alloy(self, alloy: pf_alloy_params):
+        _check(load().pf_set_alloy(self.h, ctypes.byref(alloy)), "pf_set_alloy")
+        self.alloy = alloy
+
+    def pf_alloy_residual(self, U, Uprev, Uprev2, t, F, stream=None):
+        _check(load().pf_alloy_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), float(t), _ptr(F),
+                                        _stream(stream)), "pf_alloy_residual")
+        return F
+
+    def pf_alloy_explicit(self, Uprev, t_prev, E, stream=None):
+        _check(load().pf_alloy_explicit(self.h, _ptr(Uprev), float(t_prev), _ptr(E), _stream(stream)),
+               "pf_alloy_explicit")
+        return E
+
+    def pf_alloy_jvp(self, U, Uprev, Uprev2, t, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
+        _check(load().pf_alloy_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), float(t), _ptr(v),
+                                   _ptr(F0), mode, _ptr(Jv), _stream(stream)), "pf_alloy_jvp")
+        return Jv
+
+    def pf_alloy_step(self, Uprev2, Uprev, t_prev, U, opts=None, stream=None, check=True):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        rc = load().pf_alloy_step(self.h, _ptr(Uprev2), _ptr(Uprev), float(t_prev), _ptr(U),
+                                  ctypes.byref(o), ctypes.byref(st), _stream(stream))
+        if check:
+            _check(rc, "pf_alloy_step")
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def pf_alloy_evolve(self, states, steps, t0=0.0, opts=None, stream=None):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        _check(load().pf_alloy_evolve(self.h, _ptr(states), steps, float(t0), ctypes.byref(o),
+                                      ctypes.byref(st), _stream(stream)), "pf_alloy_evolve")
+        return st.as_dict()
+
     def pf_misfit(self, U, phi_target, L_dev, dLdU=None, stream=None):
         _check(load().pf_misfit(self.h, _ptr(U), _ptr(phi_target), _ptr(L_dev), _ptr(dLdU),
                                 _stream(stream)), "pf_misfit")
@@ -285,3 +337,15 @@ def problem_for(w, gmres_m_max: int = 30, eps4=None, lam=None, theta=1.0) -> Pro
                     w.eps4 if eps4 is None else eps4, w.lam if lam is None else lam, w.D, w.delta2,
                     theta)
     return Problem(p, gmres_m_max)
+
+
+def alloy_problem_for(w, gmres_m_max: int = 30, dt=None) -> Problem:
+    """Problem in the alloy model for an inputs.AlloyWorkload."""
+    D, l_T, v_pull = w.scales()
+    p = make_params(w.dim, list(w.n), list(w.half_width), w.dt if dt is None else dt, w.eps4, w.lam, D,
+                    w.delta2, w.theta)
+    pb = Problem(p, gmres_m_max)
+    a = pf_alloy_params()
+    a.k, a.l_T, a.x_iso, a.v_pull = w.k, l_T, w.x_iso, v_pull
+    pb.pf_set_alloy(a)
+    return pb

@@ -497,6 +497,17 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
   return PF_OK;
 }
 
+// One alloy step: the explicit part at t_prev, the history rate, then
+// Newton-Krylov on F + E = 0 with the implicit part at t_prev + dt.
+int alloy_step_impl(pf_problem* pb, const double* Uprev2, const double* Uprev, double t_prev,
+                    double* U, const pf_solver_opts& o, pf_solver_stats* st, hipStream_t s) {
+  PF_TRY(ensure_load_vec(pb));
+  PF_TRY(alloy_explicit(pb, Uprev, t_prev, pb->load_vec, s));
+  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  pb->t_new = t_prev + pb->params.dt;
+  return newton_impl(pb, Uprev, pb->params.theta == 1.0 ? nullptr : pb->load_vec, U, o, st, s);
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -542,6 +553,15 @@ Geo make_geo(const pf_params& p) {
   G.Dth = p.theta * p.D;
   G.hth = 0.5 * p.theta;
   return G;
+}
+
+// The thermal entry points and the pf_alloy_* entry points each need a
+// handle of their own model.
+int require_model(const pf_problem* pb, int model) {
+  if (pb->model == model) return PF_OK;
+  set_error(model == 0 ? "handle is in the alloy model: use the pf_alloy_* calls"
+                       : "handle is in the thermal model: call pf_set_alloy first");
+  return PF_ERR_INVALID_ARG;
 }
 
 }  // namespace pf
@@ -642,10 +662,10 @@ int pf_destroy(pf_problem* pb) {
   chk(hipDeviceSynchronize(), "hipDeviceSynchronize");
   chk(pc_free(pb), "preconditioner buffers");
   double* bufs[] = {pb->red_partials, pb->red_out, pb->elem_buf, pb->vjp_partials, pb->eps_dev,
-                    pb->V, pb->Z, pb->side_buf, pb->load_vec};
+                    pb->V, pb->Z, pb->side_buf, pb->load_vec, pb->hist};
   const char* names[] = {"red_partials", "red_out", "elem_buf", "vjp_partials", "eps_dev", "V", "Z",
-                         "side_buf", "load_vec"};
-  for (int i = 0; i < 9; ++i)
+                         "side_buf", "load_vec", "hist"};
+  for (int i = 0; i < 10; ++i)
     if (bufs[i]) chk(hipFree(bufs[i]), names[i]);
   for (int i = 0; i < kNumTmp; ++i)
     if (pb->tmp_vec[i]) chk(hipFree(pb->tmp_vec[i]), "tmp_vec");
@@ -684,6 +704,7 @@ int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F,
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(F, "F"));
@@ -698,6 +719,7 @@ int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(v, "v"));
@@ -727,6 +749,7 @@ int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(w, "w"));
@@ -772,6 +795,7 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_opts(pb, opts));
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
@@ -804,6 +828,7 @@ int pf_newton_step(pf_problem* pb, const double* Uprev, double* U, const pf_solv
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_opts(pb, opts));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
@@ -824,6 +849,7 @@ int pf_newton_step_theta(pf_problem* pb, const double* Uprev2, const double* Upr
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_opts(pb, opts));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
@@ -853,6 +879,7 @@ int pf_theta_explicit(pf_problem* pb, const double* Uprev, const double* Uprev2,
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(Uprev2, "Uprev2"));
   PF_TRY(check_vec(E, "E"));
@@ -866,6 +893,7 @@ int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* o
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_opts(pb, opts));
   PF_TRY(check_vec(states, "states"));
   if (steps < 0) {
@@ -913,6 +941,7 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
     set_error("handle is NULL");
     return PF_ERR_INVALID_ARG;
   }
+  PF_TRY(require_model(pb, 0));
   PF_TRY(check_opts(pb, opts));
   if (pb->params.theta != 1.0) {
     set_error("pf_adjoint_step covers backward Euler (theta = 1) only");
@@ -949,6 +978,174 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   if (mu_prev) PF_TRY(blas_axpby(-1.0, gP, 0.0, gP, mu_prev, pb->n_dof, s));
   PF_HIP_CHECK(hipStreamSynchronize(s));
   if (stats) stats->t_total_ms = now_ms() - t0;
+  return PF_OK;
+}
+
+int pf_set_alloy(pf_problem* pb, const pf_alloy_params* a) {
+  clear_stale_error();
+  if (!pb || !a) {
+    set_error("handle or alloy parameters are NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!(a->k > 0.0 && a->k <= 1.0) || !(a->l_T > 0.0) || !std::isfinite(a->x_iso) ||
+      !std::isfinite(a->v_pull)) {
+    set_error("alloy parameters need 0 < k <= 1, l_T > 0 and finite x_iso, v_pull");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int NA = 1 << pb->geo.dim;
+  const long long need = (long long)2 * NA * pb->geo.n_elems;
+  if (pb->elem_buf_len < need) {
+    if (pb->elem_buf) PF_HIP_CHECK(hipFree(pb->elem_buf));
+    pb->elem_buf = nullptr;
+    pb->elem_buf_len = 0;
+    if (hipMalloc(&pb->elem_buf, (size_t)need * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      pb->elem_buf = nullptr;
+      set_error("out of device memory for the alloy element buffer");
+      return PF_ERR_OOM;
+    }
+    pb->elem_buf_len = need;
+  }
+  if (!pb->hist) {
+    if (hipMalloc(&pb->hist, (size_t)pb->geo.n_nodes * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      pb->hist = nullptr;
+      set_error("out of device memory for the alloy history field");
+      return PF_ERR_OOM;
+    }
+  }
+  pb->alloy = *a;
+  pb->model = 1;
+  return PF_OK;
+}
+
+int pf_alloy_residual(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                      double t, double* F, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 1));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(F, "F"));
+  hipStream_t s = S(stream);
+  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  pb->t_new = t;
+  return launch_alloy(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, s);
+}
+
+int pf_alloy_explicit(pf_problem* pb, const double* Uprev, double t_prev, double* E, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 1));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(E, "E"));
+  return alloy_explicit(pb, Uprev, t_prev, E, S(stream));
+}
+
+int pf_alloy_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                 double t, const double* v, const double* F0, int mode, double* Jv, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 1));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(v, "v"));
+  PF_TRY(check_vec(Jv, "Jv"));
+  if (mode != PF_JV_FD && mode != PF_JV_ANALYTIC) {
+    set_error("mode must be PF_JV_FD or PF_JV_ANALYTIC");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  pb->t_new = t;
+  if (mode == PF_JV_ANALYTIC)
+    return launch_alloy(pb, MODE_JVP, U, Uprev, v, nullptr, nullptr, Jv, nullptr, s);
+  const double* base = F0;
+  if (!base) {
+    PF_TRY(launch_alloy(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, pb->tmp_vec[0], nullptr,
+                        s));
+    base = pb->tmp_vec[0];
+  } else {
+    PF_TRY(check_vec(F0, "F0"));
+  }
+  PF_TRY(blas_fd_eps(pb, U, v, pb->n_dof, pb->eps_dev, s));
+  return launch_alloy(pb, MODE_FD, U, Uprev, v, base, pb->eps_dev, Jv, nullptr, s);
+}
+
+int pf_alloy_step(pf_problem* pb, const double* Uprev2, const double* Uprev, double t_prev,
+                  double* U, const pf_solver_opts* opts, pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 1));
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(U, "U"));
+  stats_reset(stats);
+  const double t0 = now_ms();
+  int rc = alloy_step_impl(pb, Uprev2, Uprev, t_prev, U, *opts, stats, S(stream));
+  if (stats) {
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int pf_alloy_evolve(pf_problem* pb, double* states, int steps, double t0,
+                    const pf_solver_opts* opts, pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 1));
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(states, "states"));
+  if (steps < 0) {
+    set_error("steps must be >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  const long long n = pb->n_dof;
+  pf_solver_stats acc;
+  stats_reset(&acc);
+  const double tstart = now_ms();
+  for (int k = 0; k < steps; ++k) {
+    double* prev = states + (long long)k * n;
+    double* next = prev + n;
+    const double* prev2 = k > 0 ? prev - n : prev;
+    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    pf_solver_stats st;
+    stats_reset(&st);
+    int rc = alloy_step_impl(pb, prev2, prev, t0 + k * pb->params.dt, next, *opts, &st, s);
+    acc.newton_its += st.newton_its;
+    acc.gmres_its_total += st.gmres_its_total;
+    acc.backtracks += st.backtracks;
+    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
+    acc.f0 = st.f0;
+    acc.f_final = st.f_final;
+    if (rc != PF_OK) {
+      acc.status = rc;
+      if (stats) *stats = acc;
+      return rc;
+    }
+  }
+  acc.t_total_ms = now_ms() - tstart;
+  if (stats) *stats = acc;
   return PF_OK;
 }
 

@@ -832,10 +832,21 @@ hipError_t hier_free(Hier<T>& H) {
   return first;
 }
 
+// Mass and stiffness scales of the two blocks: phi block (1/dt) M_c +
+// theta K_c; u block (1/dt) M + theta D K (thermal) or (1+k)/(2 dt) M +
+// theta D K (alloy, the one-sided mobility at its liquid value).
+void block_scales(const pf_problem* pb, double* sm, double* sk) {
+  const double idt = 1.0 / pb->params.dt, th = pb->params.theta;
+  sm[0] = idt;
+  sk[0] = th;
+  sm[1] = pb->model == 1 ? 0.5 * (1.0 + pb->alloy.k) * idt : idt;
+  sk[1] = th * pb->params.D;
+}
+
 template <int DIM, class T>
 int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) {
-  const double sm[2] = {1.0 / pb->params.dt, 1.0 / pb->params.dt};
-  const double sk[2] = {pb->params.theta, pb->params.theta * pb->params.D};
+  double sm[2], sk[2];
+  block_scales(pb, sm, sk);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level<T>& L = H.lv[l];
     for (int f = 0; f < 2; ++f) {
@@ -1071,8 +1082,10 @@ int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s) {
       return PF_OK;
     case PF_PC_JACOBI: {
       double Ae0[8], Ae1[8];
-      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.theta, Ae0);
-      element_table(G.dim, G.h, 1.0 / pb->params.dt, pb->params.theta * pb->params.D, Ae1);
+      double sm[2], sk[2];
+      block_scales(pb, sm, sk);
+      element_table(G.dim, G.h, sm[0], sk[0], Ae0);
+      element_table(G.dim, G.h, sm[1], sk[1], Ae1);
       hipLaunchKernelGGL(k_jacobi, dim3(blocks(n)), dim3(kT), 0, s, G, (const double*)st->coef0,
                          reinterpret_cast<const double2*>(r), reinterpret_cast<double2*>(z),
                          Ae0[0], Ae1[0]);

@@ -51,6 +51,16 @@ struct Geo {
 
 Geo make_geo(const pf_params& p);
 
+// Alloy-model constants of one element-kernel launch (host-computed).
+struct AlloyConst {
+  double omk;       // 1 - k
+  double hopk;      // (1 + k)/2
+  double g4a, g4b;  // G4 = g4a x + g4b at the launch's time level
+  double x0, h0;    // node x coordinate = x0 + i h0 (axis 0)
+  double theta;     // time weight of this launch (1 for the explicit part)
+  int use_hist;     // 0: the history rate is zero
+};
+
 // Element-loop modes of the residual kernel family.
 // MODE_VJPU: (dF/dU)^T w only (the operator of the transposed Krylov solve).
 enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4 };
@@ -69,6 +79,20 @@ int launch_residual_family(pf_problem* pb, int mode, const double* U, const doub
                            const double* v, const double* F0, const double* eps_dev,
                            double* out0, double* out1, double* gparams_partial,
                            hipStream_t s, double* coef = nullptr);
+// Node sums of the element buffer (pf_residual.hip): out0 = sums, or
+// (sums - F0)/eps when fd != 0.
+int launch_gather2(pf_problem* pb, double* out0, const double* F0, const double* eps_dev, int fd,
+                   hipStream_t s);
+
+// Alloy model (pf_alloy.hip).  launch_alloy: modes RES, FD, JVP at pb->t_new
+// with the history rate pb->hist; explicit: the spatial operator at (U, t)
+// scaled by 1 - theta.
+AlloyConst alloy_const(const pf_problem* pb, double t, double theta, int use_hist);
+int launch_alloy(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
+                 const double* F0, const double* eps_dev, double* out0, double* coef,
+                 hipStream_t s);
+int alloy_explicit(pf_problem* pb, const double* Un, double t_n, double* E, hipStream_t s);
+int alloy_history(pf_problem* pb, const double* Un, const double* Unm1, hipStream_t s);
 
 // ----------------------------------------------------------------- BLAS-1 (pf_blas.hip)
 // Deterministic reductions over n doubles: fixed grid, fixed order.
@@ -143,6 +167,13 @@ struct pf_problem {
   double* eps_dev;       // FD epsilon (device scalar)
   double* tmp_vec[6];    // work vectors of n_dof doubles (kNumTmp)
   double* load_vec;      // theta < 1: the explicit part E of the step (lazy)
+
+  // alloy model (pf_set_alloy): parameters, the history rate
+  // (1 - theta)(phi^n - phi^(n-1))/dt per node, and the time of the implicit part
+  int model;             // 0 thermal, 1 alloy
+  pf_alloy_params alloy;
+  double* hist;          // n_nodes doubles
+  double t_new;
 
   // FGMRES basis
   double* V;  // (m+1) * n_dof

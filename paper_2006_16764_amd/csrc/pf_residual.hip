@@ -198,10 +198,27 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
 
 }  // namespace
 
+int launch_gather2(pf_problem* pb, double* out0, const double* F0, const double* eps_dev, int fd,
+                   hipStream_t s) {
+  const Geo& G = pb->geo;
+  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
+  if (G.dim == 3)
+    hipLaunchKernelGGL((k_gather<3, 2>), dim3(nb), dim3(256), 0, s, G, pb->elem_buf,
+                       reinterpret_cast<double2*>(out0), nullptr,
+                       reinterpret_cast<const double2*>(F0), eps_dev, fd);
+  else
+    hipLaunchKernelGGL((k_gather<2, 2>), dim3(nb), dim3(256), 0, s, G, pb->elem_buf,
+                       reinterpret_cast<double2*>(out0), nullptr,
+                       reinterpret_cast<const double2*>(F0), eps_dev, fd);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
 int launch_residual_family(pf_problem* pb, int mode, const double* U, const double* Uprev,
                            const double* v, const double* F0, const double* eps_dev,
                            double* out0, double* out1, double* vjp_part, hipStream_t s,
                            double* coef) {
+  if (pb->model == 1) return launch_alloy(pb, mode, U, Uprev, v, F0, eps_dev, out0, coef, s);
   if (pb->geo.dim == 3)
     return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
   return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);

@@ -198,3 +198,98 @@ def random_state(dim: int, n: Sequence[int], seed: int, amp: float = 0.9) -> np.
     U[:, 0] = rng.uniform(-amp, amp, n_nodes)
     U[:, 1] = rng.uniform(-1.0, 1.0, n_nodes)
     return U
+
+
+# ---------------------------------------------------------------- alloy workloads
+# Directional solidification of a dilute binary alloy (Sec. 4.3, Table
+# ds_parameters): Al-Cu, k = 0.14, m = -2.6 K/wt%, c_inf = 3 wt%, lambda = 10,
+# D_L = 3e-9 m^2/s, d0 = 5e-9 m, G = 1e4 K/m, R = 1e-2 m/s, eps = 0.01, and the
+# scales of Sec. 4.3: W0 = d0 lambda/a1, tau0 = d0^2 a2 lambda^3/(D_L a1^2),
+# D = D_L tau0/W0^2, a1 = 0.8839, a2 = 0.6267.  The thermal length
+# l_T = |m| c_inf (1 - k)/(k G) and the pulling speed R are expressed in W0 and
+# tau0.  Meshes have h = 0.8; theta = 1/2, dt = 0.002.
+@dataclasses.dataclass(frozen=True)
+class AlloyWorkload:
+    """Box mesh [0, n0 h] x [0, n1 h] (x [0, n2 h]) in physical x; the mesh's own
+    coordinates are centred, x_mesh = x_phys - n0 h / 2."""
+    name: str
+    dim: int
+    n: Tuple[int, ...]
+    dt: float
+    theta: float
+    steps: int
+    seed: int
+    x_front: float = 8.0      # initial interface position (physical x)
+    amp: float = 0.5          # amplitude of the random interface perturbation
+    h: float = 0.8
+    k: float = 0.14
+    eps4: float = 0.01
+    lam: float = 10.0
+    u0: float = -1.0
+    delta2: float = 1e-16
+
+    @property
+    def half_width(self) -> Tuple[float, ...]:
+        return tuple(0.5 * self.h * nk for nk in self.n)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod([nk + 1 for nk in self.n]))
+
+    @property
+    def n_dof(self) -> int:
+        return 2 * self.n_nodes
+
+    @property
+    def n_elems(self) -> int:
+        return int(np.prod(self.n))
+
+    def scales(self):
+        """(D, l_T, v_pull) in units of W0 and tau0 from the table's values."""
+        a1, a2 = 0.8839, 0.6267
+        d0, DL, m, cinf, G, R = 5e-9, 3e-9, -2.6, 3.0, 1e4, 1e-2
+        W0 = d0 * self.lam / a1
+        tau0 = d0 ** 2 * a2 * self.lam ** 3 / (DL * a1 ** 2)
+        D = DL * tau0 / W0 ** 2
+        l_T = abs(m) * cinf * (1.0 - self.k) / (self.k * G) / W0
+        return D, l_T, R * tau0 / W0
+
+    @property
+    def x_iso(self) -> float:
+        """Isotherm of G4 = 0 at t = 0, placed at the initial front (mesh coordinate)."""
+        return self.x_front - self.half_width[0]
+
+
+ALLOY_WORKLOADS = {
+    "alloy2d_48x16": AlloyWorkload("alloy2d_48x16", 2, (48, 16), 0.002, 0.5, 5, 21),
+    "alloy2d_1024x256": AlloyWorkload("alloy2d_1024x256", 2, (1024, 256), 0.002, 0.5, 10, 22),
+    "alloy3d_1024x256x256": AlloyWorkload("alloy3d_1024x256x256", 3, (1024, 256, 256), 0.002, 0.5, 2, 23),
+}
+
+
+def alloy_workload(name: str) -> AlloyWorkload:
+    return ALLOY_WORKLOADS[name]
+
+
+def alloy_initial_state(w: AlloyWorkload, chunk: int = 1 << 22) -> np.ndarray:
+    """phi = -tanh((x - x_front - d(y, z))/sqrt(2)), u = u0.
+
+    The paper starts from a sharp front at x = 8 with a small random
+    perturbation; here the front is the diffuse equilibrium profile and d is a
+    seeded uniform perturbation of amplitude amp on every transverse node
+    column.  x is the physical coordinate (x_mesh + n0 h / 2).
+    """
+    nn = [nk + 1 for nk in w.n]
+    total = int(np.prod(nn))
+    cols = int(np.prod(nn[1:]))
+    rng = np.random.default_rng(w.seed)
+    d = rng.uniform(-w.amp, w.amp, cols)
+    x = np.arange(nn[0]) * w.h
+    U = np.empty((total, 2))
+    U[:, 1] = w.u0
+    # node = i + nn0 * column
+    for c0 in range(0, cols, max(1, chunk // nn[0])):
+        c1 = min(cols, c0 + max(1, chunk // nn[0]))
+        phi = -np.tanh((x[None, :] - w.x_front - d[c0:c1, None]) / math.sqrt(2.0))
+        U[c0 * nn[0]:c1 * nn[0], 0] = phi.reshape(-1)
+    return U

@@ -46,6 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(pf_params), offsetof(pf_params, dt), offsetof(pf_params, delta2), offsetof(pf_params, half_width), offsetof(pf_params, theta));
   printf("%zu %zu %zu\\n", sizeof(pf_solver_opts), offsetof(pf_solver_opts, eta0), offsetof(pf_solver_opts, pc_precision));
   printf("%zu %zu %zu\\n", sizeof(pf_solver_stats), offsetof(pf_solver_stats, fnorm), offsetof(pf_solver_stats, t_total_ms));
+  printf("%zu %zu\\n", sizeof(pf_alloy_params), offsetof(pf_alloy_params, v_pull));
   return 0;
 }
 """)
@@ -55,7 +56,8 @@ int main(void) {
     P, O, S = binding.pf_params, binding.pf_solver_opts, binding.pf_solver_stats
     expect = [ctypes.sizeof(P), P.dt.offset, P.delta2.offset, P.half_width.offset, P.theta.offset,
               ctypes.sizeof(O), O.eta0.offset, O.pc_precision.offset,
-              ctypes.sizeof(S), S.fnorm.offset, S.t_total_ms.offset]
+              ctypes.sizeof(S), S.fnorm.offset, S.t_total_ms.offset,
+              ctypes.sizeof(binding.pf_alloy_params), binding.pf_alloy_params.v_pull.offset]
     assert [int(v) for v in out] == expect
 
 
