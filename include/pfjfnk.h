@@ -271,7 +271,8 @@ int pf_dot(pf_problem* pb, const double* x, const double* y, double* out_dev, vo
  *                     (D (1 - phi^n)/2 grad u^n, grad psi) ].
  * The anisotropy, dt, theta, lambda, D, delta2 come from pf_params.  The
  * preconditioner keeps the block form of Eq. pre with the phi block
- * (1/dt) M_c + theta K_c (c = cell mean of a^2) and the u block
+ * (1/dt) M_c + theta K_c (c = cell mean of cu a^2, the mobility factor of the
+ * time term) and the u block
  * (1+k)/(2 dt) M + theta D K (the one-sided mobility taken as its liquid
  * value).  A handle switched to this model accepts only the pf_alloy_* calls
  * below, pf_precond_setup/apply, pf_misfit and pf_dot; no VJP or adjoint.

@@ -773,6 +773,14 @@ int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, v
     set_error("invalid preconditioner kind or precision");
     return PF_ERR_INVALID_ARG;
   }
+  if (pb->model == 1) {
+    // alloy: the phi-block coefficient (cell mean of cu a^2) comes out of the
+    // residual kernel; the residual itself is discarded
+    hipStream_t s = S(stream);
+    PF_TRY(launch_alloy(pb, MODE_RES, U, U, nullptr, nullptr, nullptr, pb->tmp_vec[0],
+                        pc_coef_buffer(pb), s));
+    return pc_setup_prepared(pb, kind, precision, s);
+  }
   return pc_setup(pb, U, kind, precision, S(stream));
 }
 

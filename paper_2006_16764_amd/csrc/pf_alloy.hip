@@ -55,7 +55,8 @@ __device__ __forceinline__ double val(Dual x) { return x.v; }
 
 // Pointwise terms of the alloy residual: s1, f1 (phi rows: value and flux
 // parts), s2, f2 (u rows).  hist = (1 - theta)(phi^n - phi^(n-1))/dt, x the
-// point's coordinate along axis 0.  a2 receives a^2 (preconditioner).
+// point's coordinate along axis 0.  a2 receives cu a^2, the mobility factor of
+// the time term (the preconditioner's phi-block coefficient).
 template <int DIM, class T>
 __device__ __forceinline__ void alloy_point(const Geo& G, const AlloyConst& C, const T& phi,
                                             const T (&g)[3], const T& u, const T (&gu)[3],
@@ -97,7 +98,7 @@ __device__ __forceinline__ void alloy_point(const Geo& G, const AlloyConst& C, c
       f2[k] = T{};
     }
   }
-  a2 = val(aa);
+  a2 = val(cu * aa);
 }
 
 // Residual: gradient fields {phi, u}; value fields {phi - phi^n, u - u^n, hist, x}.
