@@ -293,3 +293,90 @@ def alloy_initial_state(w: AlloyWorkload, chunk: int = 1 << 22) -> np.ndarray:
         phi = -np.tanh((x[None, :] - w.x_front - d[c0:c1, None]) / math.sqrt(2.0))
         U[c0 * nn[0]:c1 * nn[0], 0] = phi.reshape(-1)
     return U
+
+
+# ---------------------------------------------------------------- free-growth workloads
+# Pure-melt dendrite of Sec. 4.1 (Table parameters): phi in [0, 1] (1 solid),
+# temperature T; eps = 0.005, alpha = 4, Lcp = 1, beta = 1/Gamma = 191.82,
+# undercooling Delta = 0.55; the domain [0, 4.5]^2 with h = 0.03 (150^2
+# elements; the table's W is taken from its relation W = h/0.4), Crank-Nicolson.
+@dataclasses.dataclass(frozen=True)
+class FreeGrowthWorkload:
+    """Box [0, n0 h] x [0, n1 h] in physical coordinates; the mesh's own
+    coordinates are centred (x_mesh = x_phys - n h / 2).  A quarter seed sits
+    at the corner x_phys = 0 (the zero-Neumann walls are symmetry planes)."""
+    name: str
+    dim: int
+    n: Tuple[int, ...]
+    order: int
+    dt: float
+    steps: int
+    theta: float = 0.5
+    h: float = 0.03
+    eps4: float = 0.005
+    beta: float = 191.82
+    alpha: float = 4.0
+    Lcp: float = 1.0
+    Tm: float = 1.0
+    undercooling: float = 0.55
+    r0: float = 0.3
+    delta2: float = 1e-16
+
+    @property
+    def Gamma(self) -> float:
+        return 1.0 / self.beta
+
+    @property
+    def W(self) -> float:
+        return self.h / 0.4
+
+    @property
+    def half_width(self) -> Tuple[float, ...]:
+        return tuple(0.5 * self.h * nk for nk in self.n)
+
+    @property
+    def nodes_per_axis(self) -> Tuple[int, ...]:
+        return tuple(self.order * nk + 1 for nk in self.n)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod(self.nodes_per_axis))
+
+    @property
+    def n_dof(self) -> int:
+        return 2 * self.n_nodes
+
+    @property
+    def n_elems(self) -> int:
+        return int(np.prod(self.n))
+
+
+FREEGROWTH_WORKLOADS = {
+    "freegrowth2d_150_q1": FreeGrowthWorkload("freegrowth2d_150_q1", 2, (150, 150), 1, 1e-4, 20),
+    "freegrowth2d_150_q2": FreeGrowthWorkload("freegrowth2d_150_q2", 2, (150, 150), 2, 1e-4, 20),
+    # the same model and spacing on a 2048^2-element box: a throughput size
+    "freegrowth2d_2048_q2": FreeGrowthWorkload("freegrowth2d_2048_q2", 2, (2048, 2048), 2, 1e-4, 2),
+}
+
+
+def freegrowth_workload(name: str) -> FreeGrowthWorkload:
+    return FREEGROWTH_WORKLOADS[name]
+
+
+def freegrowth_initial_state(w: FreeGrowthWorkload) -> np.ndarray:
+    """phi = (1 - tanh((rho - r(angle))/(2 W)))/2 around the corner, r = r0 g_s(angle)
+    = r0 (1 + eps4 cos 4 angle) (2-D), T = Tm - Delta everywhere.
+
+    The paper's seed is a sharp disc of radius 0.3 g_s; here it is the diffuse
+    equilibrium profile of the same radius, and the melt starts at the
+    undercooled temperature Tm - Delta."""
+    axes = [np.linspace(0.0, w.h * w.n[k], w.nodes_per_axis[k]) for k in range(w.dim)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    X = np.stack([g.transpose(tuple(range(w.dim))[::-1]).reshape(-1) for g in grids], axis=1)
+    rho = np.sqrt((X ** 2).sum(axis=1))
+    ang = np.arctan2(X[:, 1], X[:, 0])
+    r = w.r0 * (1.0 + w.eps4 * np.cos(4.0 * ang))
+    U = np.empty((X.shape[0], 2))
+    U[:, 0] = 0.5 * (1.0 - np.tanh((rho - r) / (2.0 * w.W)))
+    U[:, 1] = w.Tm - w.undercooling
+    return U
