@@ -75,7 +75,9 @@ extern "C" {
  * in 2-D); half_width[k] > 0.  dt > 0, D > 0, delta2 > 0 (regularises the
  * anisotropy where grad phi = 0; 1e-16 is the default reading); theta in
  * (0, 1]: the time weight of Eq. dpf (1 backward Euler, 1/2 the trapezoidal
- * or Crank-Nicolson rule). */
+ * or Crank-Nicolson rule).  order: Lagrange element order, 1 (bilinear /
+ * trilinear; 0 is read as 1) or 2 (biquadratic, 2-D, free-growth model only):
+ * order-2 meshes have 2 n[k] + 1 nodes per axis. */
 typedef struct {
   int dim;
   int n[3];
@@ -86,6 +88,7 @@ typedef struct {
   double D;
   double delta2;
   double theta;
+  int order;
 } pf_params;
 
 /* Newton-Krylov options (Sec. 2.2).  The forcing term follows Eqs. force1 to
@@ -313,6 +316,63 @@ int pf_alloy_step(pf_problem* pb, const double* Uprev2, const double* Uprev, dou
  * the first step takes U^(-1) = U^0). */
 int pf_alloy_evolve(pf_problem* pb, double* states, int steps, double t0,
                     const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Free-growth model: a pure melt with phi in [0, 1] (1 solid) and temperature
+ * T (Sec. 4.1, Eqs. pf1, g1, gs, temp1, with the weight theta of Eq. theta),
+ * on order-1 or order-2 elements.  The part of the step residual that depends
+ * on the new state U = (phi, T) is
+ *
+ *   F1_i = (a^2 (phi - phi^n)/dt, psi_i) + theta beta Gamma (J(grad phi), grad psi_i)
+ *          + theta (G2(phi, T), psi_i)
+ *   F3_i = ((T - T^n)/dt, psi_i) + theta alpha (grad T, grad psi_i) - (Lcp phihat, psi_i)
+ *   G2   = beta Gamma phi (1 - phi)(1 - 2 phi)/W^2 - 5 beta (Tm - T) phi^2 (1 - phi)^2 / W
+ *
+ * with a, J of the thermal model (eps4, delta2 from pf_params), phihat of Eq.
+ * theta, and E = (1 - theta) times the spatial terms at U^n.  The second
+ * field of every vector is T.  The preconditioner is Eq. pre with the blocks
+ * of Eqs. m11 and m22: (1/dt) M_c + theta beta Gamma K_c (c = cell mean of
+ * a^2) and (1/dt) M + theta alpha K; on order-2 meshes it is the order-1
+ * operator on the grid of order-2 nodes (each element split into 2^dim
+ * cells), a spectrally equivalent stand-in.  pf_params.D and lambda are not
+ * used by this model.  A handle switched to it accepts only the pf_fg_* calls,
+ * pf_precond_setup/apply, pf_dot.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double beta;   /* kinetic coefficient */
+  double Gamma;  /* 1/beta in the paper's table; > 0 */
+  double W;      /* interface width, > 0 */
+  double alpha;  /* thermal diffusivity, > 0 */
+  double Lcp;    /* latent heat over heat capacity */
+  double Tm;     /* melting temperature */
+} pf_freegrowth_params;
+
+/* Switch the handle to the free-growth model (host; allocates the history
+ * field and the element buffer, 16 (order 1, 2-D), 16 (order 1, 3-D: 8
+ * corners) or 18 (order 2) doubles per element).  PF_ERR_INVALID_ARG,
+ * PF_ERR_OOM. */
+int pf_set_freegrowth(pf_problem* pb, const pf_freegrowth_params* fg);
+
+/* [async] F = implicit part from Uprev = U^n and Uprev2 = U^(n-1). */
+int pf_fg_residual(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                   double* F, void* stream);
+
+/* [async] E = part of the step fixed by Uprev = U^n. */
+int pf_fg_explicit(pf_problem* pb, const double* Uprev, double* E, void* stream);
+
+/* [async] Jv of the implicit part (modes as pf_jvp; the analytic product is
+ * forward-mode differentiation of the pointwise terms on dual numbers). */
+int pf_fg_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+              const double* v, const double* F0, int mode, double* Jv, void* stream);
+
+/* [sync] One theta step (Newton-Krylov on F + E = 0 from U_inout). */
+int pf_fg_step(pf_problem* pb, const double* Uprev2, const double* Uprev, double* U_inout,
+               const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
+
+/* [sync] steps theta steps from states[0] (layout as pf_evolve; the first
+ * step takes U^(-1) = U^0). */
+int pf_fg_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
+                 pf_solver_stats* stats, void* stream);
 
 /* Thread-local message describing the last error ("" if none). */
 const char* pf_last_error(void);

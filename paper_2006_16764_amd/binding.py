@@ -45,12 +45,18 @@ ERROR_NAMES = {
 class pf_params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("half_width", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("eps4", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("D", ctypes.c_double), ("delta2", ctypes.c_double), ("theta", ctypes.c_double)]
+                ("D", ctypes.c_double), ("delta2", ctypes.c_double), ("theta", ctypes.c_double),
+                ("order", ctypes.c_int)]
 
 
 class pf_alloy_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("l_T", ctypes.c_double), ("x_iso", ctypes.c_double),
                 ("v_pull", ctypes.c_double)]
+
+
+class pf_freegrowth_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("Gamma", ctypes.c_double), ("W", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("Lcp", ctypes.c_double), ("Tm", ctypes.c_double)]
 
 
 class pf_solver_opts(ctypes.Structure):
@@ -112,6 +118,14 @@ _SIGS = {
     "pf_alloy_evolve": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.c_double,
                                        ctypes.POINTER(pf_solver_opts), ctypes.POINTER(pf_solver_stats),
                                        _VP]),
+    "pf_set_freegrowth": (ctypes.c_int, [_VP, ctypes.POINTER(pf_freegrowth_params)]),
+    "pf_fg_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pf_fg_explicit": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "pf_fg_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP]),
+    "pf_fg_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
+                                  ctypes.POINTER(pf_solver_stats), _VP]),
+    "pf_fg_evolve": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.POINTER(pf_solver_opts),
+                                    ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_last_error": (ctypes.c_char_p, []),
 }
 
@@ -169,7 +183,7 @@ def default_opts(**kw) -> pf_solver_opts:
     return o
 
 
-def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16, theta=1.0) -> pf_params:
+def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16, theta=1.0, order=1) -> pf_params:
     p = pf_params()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -178,6 +192,7 @@ def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16, theta=1.0) -
         p.n[k] = int(nn[k])
         p.half_width[k] = float(hw[k])
     p.dt, p.eps4, p.lambda_, p.D, p.delta2, p.theta = dt, eps4, lam, D, delta2, theta
+    p.order = order
     return p
 
 
@@ -323,6 +338,42 @@ class Problem:
                                       ctypes.byref(st), _stream(stream)), "pf_alloy_evolve")
         return st.as_dict()
 
+    def pf_set_freegrowth(self, fgp: pf_freegrowth_params):
+        _check(load().pf_set_freegrowth(self.h, ctypes.byref(fgp)), "pf_set_freegrowth")
+        self.fg = fgp
+
+    def pf_fg_residual(self, U, Uprev, Uprev2, F, stream=None):
+        _check(load().pf_fg_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), _ptr(F),
+                                     _stream(stream)), "pf_fg_residual")
+        return F
+
+    def pf_fg_explicit(self, Uprev, E, stream=None):
+        _check(load().pf_fg_explicit(self.h, _ptr(Uprev), _ptr(E), _stream(stream)), "pf_fg_explicit")
+        return E
+
+    def pf_fg_jvp(self, U, Uprev, Uprev2, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
+        _check(load().pf_fg_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), _ptr(v), _ptr(F0), mode,
+                                _ptr(Jv), _stream(stream)), "pf_fg_jvp")
+        return Jv
+
+    def pf_fg_step(self, Uprev2, Uprev, U, opts=None, stream=None, check=True):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        rc = load().pf_fg_step(self.h, _ptr(Uprev2), _ptr(Uprev), _ptr(U), ctypes.byref(o),
+                               ctypes.byref(st), _stream(stream))
+        if check:
+            _check(rc, "pf_fg_step")
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def pf_fg_evolve(self, states, steps, opts=None, stream=None):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        _check(load().pf_fg_evolve(self.h, _ptr(states), steps, ctypes.byref(o), ctypes.byref(st),
+                                   _stream(stream)), "pf_fg_evolve")
+        return st.as_dict()
+
     def pf_misfit(self, U, phi_target, L_dev, dLdU=None, stream=None):
         _check(load().pf_misfit(self.h, _ptr(U), _ptr(phi_target), _ptr(L_dev), _ptr(dLdU),
                                 _stream(stream)), "pf_misfit")
@@ -348,4 +399,15 @@ def alloy_problem_for(w, gmres_m_max: int = 30, dt=None) -> Problem:
     a = pf_alloy_params()
     a.k, a.l_T, a.x_iso, a.v_pull = w.k, l_T, w.x_iso, v_pull
     pb.pf_set_alloy(a)
+    return pb
+
+
+def freegrowth_problem_for(w, gmres_m_max: int = 30, dt=None) -> Problem:
+    """Problem in the free-growth model for an inputs.FreeGrowthWorkload."""
+    p = make_params(w.dim, list(w.n), list(w.half_width), w.dt if dt is None else dt, w.eps4, 0.0, 1.0,
+                    w.delta2, w.theta, w.order)
+    pb = Problem(p, gmres_m_max)
+    f = pf_freegrowth_params()
+    f.beta, f.Gamma, f.W, f.alpha, f.Lcp, f.Tm = w.beta, w.Gamma, w.W, w.alpha, w.Lcp, w.Tm
+    pb.pf_set_freegrowth(f)
     return pb

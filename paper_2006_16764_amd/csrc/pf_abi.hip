@@ -141,6 +141,15 @@ int check_params(const pf_params* p) {
     set_error("theta must be in (0, 1]");
     return PF_ERR_INVALID_ARG;
   }
+  const int ord = p->order == 0 ? 1 : p->order;
+  if (ord != 1 && ord != 2) {
+    set_error("order must be 1 or 2");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (ord == 2 && p->dim != 2) {
+    set_error("order-2 elements are 2-D only");
+    return PF_ERR_INVALID_ARG;
+  }
   return PF_OK;
 }
 
@@ -503,8 +512,17 @@ int alloy_step_impl(pf_problem* pb, const double* Uprev2, const double* Uprev, d
                     double* U, const pf_solver_opts& o, pf_solver_stats* st, hipStream_t s) {
   PF_TRY(ensure_load_vec(pb));
   PF_TRY(alloy_explicit(pb, Uprev, t_prev, pb->load_vec, s));
-  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
   pb->t_new = t_prev + pb->params.dt;
+  return newton_impl(pb, Uprev, pb->params.theta == 1.0 ? nullptr : pb->load_vec, U, o, st, s);
+}
+
+// One free-growth step: explicit part, history rate, then Newton-Krylov.
+int fg_step_impl(pf_problem* pb, const double* Uprev2, const double* Uprev, double* U,
+                 const pf_solver_opts& o, pf_solver_stats* st, hipStream_t s) {
+  PF_TRY(ensure_load_vec(pb));
+  PF_TRY(fg_explicit(pb, Uprev, pb->load_vec, s));
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
   return newton_impl(pb, Uprev, pb->params.theta == 1.0 ? nullptr : pb->load_vec, U, o, st, s);
 }
 
@@ -523,11 +541,13 @@ Geo make_geo(const pf_params& p) {
   G.n_nodes = 1;
   G.n_elems = 1;
   G.jac = 1.0;
+  // order 2: the grid of element nodes, viewed as 2 n cells of width h/2
+  const int sub = p.order == 2 ? 2 : 1;
   for (int k = 0; k < 3; ++k) {
     if (k < p.dim) {
-      G.n[k] = p.n[k];
-      G.nn[k] = p.n[k] + 1;
-      G.h[k] = 2.0 * p.half_width[k] / p.n[k];
+      G.n[k] = sub * p.n[k];
+      G.nn[k] = sub * p.n[k] + 1;
+      G.h[k] = 2.0 * p.half_width[k] / (sub * p.n[k]);
       G.ih[k] = 1.0 / G.h[k];
       G.jac *= 0.5 * G.h[k];
     } else {
@@ -558,9 +578,18 @@ Geo make_geo(const pf_params& p) {
 // The thermal entry points and the pf_alloy_* entry points each need a
 // handle of their own model.
 int require_model(const pf_problem* pb, int model) {
-  if (pb->model == model) return PF_OK;
-  set_error(model == 0 ? "handle is in the alloy model: use the pf_alloy_* calls"
-                       : "handle is in the thermal model: call pf_set_alloy first");
+  static const char* names[3] = {"thermal (pf_residual, pf_newton_step, ...)",
+                                 "alloy (pf_set_alloy, pf_alloy_*)",
+                                 "free-growth (pf_set_freegrowth, pf_fg_*)"};
+  if (pb->model == model) {
+    if (model != 2 && pb->params.order == 2) {
+      set_error("order-2 elements are available in the free-growth model only");
+      return PF_ERR_INVALID_ARG;
+    }
+    return PF_OK;
+  }
+  set_error(std::string("this call needs a handle in the ") + names[model] + " model; the handle is in the " +
+            names[pb->model] + " model");
   return PF_ERR_INVALID_ARG;
 }
 
@@ -605,7 +634,8 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   pf_problem* pb = new pf_problem();
   std::memset(pb, 0, sizeof(*pb));
   pb->params = *params;
-  pb->geo = make_geo(*params);
+  if (pb->params.order == 0) pb->params.order = 1;
+  pb->geo = make_geo(pb->params);
   pb->n_dof = 2 * pb->geo.n_nodes;
   pb->gmres_m_max = gmres_m_max;
   PF_HIP_CHECK(hipGetDevice(&pb->device));
@@ -685,6 +715,10 @@ int pf_set_params(pf_problem* pb, const pf_params* p) {
     set_error("mesh of pf_set_params differs from the handle");
     return PF_ERR_INVALID_ARG;
   }
+  if ((p->order == 2) != (pb->params.order == 2)) {
+    set_error("element order of pf_set_params differs from the handle");
+    return PF_ERR_INVALID_ARG;
+  }
   for (int k = 0; k < p->dim; ++k) {
     if (p->n[k] != pb->params.n[k] || p->half_width[k] != pb->params.half_width[k]) {
       set_error("mesh of pf_set_params differs from the handle");
@@ -692,7 +726,8 @@ int pf_set_params(pf_problem* pb, const pf_params* p) {
     }
   }
   pb->params = *p;
-  pb->geo = make_geo(*p);
+  if (pb->params.order == 0) pb->params.order = 1;
+  pb->geo = make_geo(pb->params);
   return PF_OK;
 }
 
@@ -773,12 +808,12 @@ int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, v
     set_error("invalid preconditioner kind or precision");
     return PF_ERR_INVALID_ARG;
   }
-  if (pb->model == 1) {
-    // alloy: the phi-block coefficient (cell mean of cu a^2) comes out of the
-    // residual kernel; the residual itself is discarded
+  if (pb->model != 0) {
+    // alloy / free growth: the phi-block coefficient (cell mean of cu a^2,
+    // resp. a^2) comes out of the residual kernel; the residual is discarded
     hipStream_t s = S(stream);
-    PF_TRY(launch_alloy(pb, MODE_RES, U, U, nullptr, nullptr, nullptr, pb->tmp_vec[0],
-                        pc_coef_buffer(pb), s));
+    PF_TRY(launch_residual_family(pb, MODE_RES, U, U, nullptr, nullptr, nullptr, pb->tmp_vec[0],
+                                  nullptr, nullptr, s, pc_coef_buffer(pb)));
     return pc_setup_prepared(pb, kind, precision, s);
   }
   return pc_setup(pb, U, kind, precision, S(stream));
@@ -995,6 +1030,10 @@ int pf_set_alloy(pf_problem* pb, const pf_alloy_params* a) {
     set_error("handle or alloy parameters are NULL");
     return PF_ERR_INVALID_ARG;
   }
+  if (pb->params.order == 2) {
+    set_error("the alloy model uses order-1 elements");
+    return PF_ERR_INVALID_ARG;
+  }
   if (!(a->k > 0.0 && a->k <= 1.0) || !(a->l_T > 0.0) || !std::isfinite(a->x_iso) ||
       !std::isfinite(a->v_pull)) {
     set_error("alloy parameters need 0 < k <= 1, l_T > 0 and finite x_iso, v_pull");
@@ -1040,7 +1079,7 @@ int pf_alloy_residual(pf_problem* pb, const double* U, const double* Uprev, cons
   PF_TRY(check_vec(Uprev2, "Uprev2"));
   PF_TRY(check_vec(F, "F"));
   hipStream_t s = S(stream);
-  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
   pb->t_new = t;
   return launch_alloy(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, s);
 }
@@ -1075,7 +1114,7 @@ int pf_alloy_jvp(pf_problem* pb, const double* U, const double* Uprev, const dou
     return PF_ERR_INVALID_ARG;
   }
   hipStream_t s = S(stream);
-  PF_TRY(alloy_history(pb, Uprev, Uprev2, s));
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
   pb->t_new = t;
   if (mode == PF_JV_ANALYTIC)
     return launch_alloy(pb, MODE_JVP, U, Uprev, v, nullptr, nullptr, Jv, nullptr, s);
@@ -1140,6 +1179,170 @@ int pf_alloy_evolve(pf_problem* pb, double* states, int steps, double t0,
     pf_solver_stats st;
     stats_reset(&st);
     int rc = alloy_step_impl(pb, prev2, prev, t0 + k * pb->params.dt, next, *opts, &st, s);
+    acc.newton_its += st.newton_its;
+    acc.gmres_its_total += st.gmres_its_total;
+    acc.backtracks += st.backtracks;
+    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
+    acc.f0 = st.f0;
+    acc.f_final = st.f_final;
+    if (rc != PF_OK) {
+      acc.status = rc;
+      if (stats) *stats = acc;
+      return rc;
+    }
+  }
+  acc.t_total_ms = now_ms() - tstart;
+  if (stats) *stats = acc;
+  return PF_OK;
+}
+
+int pf_set_freegrowth(pf_problem* pb, const pf_freegrowth_params* f) {
+  clear_stale_error();
+  if (!pb || !f) {
+    set_error("handle or free-growth parameters are NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!(f->Gamma > 0.0) || !(f->W > 0.0) || !(f->alpha > 0.0) || !std::isfinite(f->beta) ||
+      !std::isfinite(f->Gamma) || !std::isfinite(f->Lcp) || !std::isfinite(f->Tm)) {
+    set_error("free-growth parameters need Gamma, W, alpha > 0 and finite beta, Lcp, Tm");
+    return PF_ERR_INVALID_ARG;
+  }
+  pb->fg = *f;
+  const long long need = fg_elem_buf_len(pb);
+  if (pb->elem_buf_len < need) {
+    if (pb->elem_buf) PF_HIP_CHECK(hipFree(pb->elem_buf));
+    pb->elem_buf = nullptr;
+    pb->elem_buf_len = 0;
+    if (hipMalloc(&pb->elem_buf, (size_t)need * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      pb->elem_buf = nullptr;
+      set_error("out of device memory for the free-growth element buffer");
+      return PF_ERR_OOM;
+    }
+    pb->elem_buf_len = need;
+  }
+  if (!pb->hist) {
+    if (hipMalloc(&pb->hist, (size_t)pb->geo.n_nodes * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      pb->hist = nullptr;
+      set_error("out of device memory for the history field");
+      return PF_ERR_OOM;
+    }
+  }
+  pb->model = 2;
+  return PF_OK;
+}
+
+int pf_fg_residual(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+                   double* F, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 2));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(F, "F"));
+  hipStream_t s = S(stream);
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
+  return launch_fg(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, s);
+}
+
+int pf_fg_explicit(pf_problem* pb, const double* Uprev, double* E, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 2));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(E, "E"));
+  return fg_explicit(pb, Uprev, E, S(stream));
+}
+
+int pf_fg_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* Uprev2,
+              const double* v, const double* F0, int mode, double* Jv, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 2));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(v, "v"));
+  PF_TRY(check_vec(Jv, "Jv"));
+  if (mode != PF_JV_FD && mode != PF_JV_ANALYTIC) {
+    set_error("mode must be PF_JV_FD or PF_JV_ANALYTIC");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  PF_TRY(history_rate(pb, Uprev, Uprev2, s));
+  if (mode == PF_JV_ANALYTIC)
+    return launch_fg(pb, MODE_JVP, U, Uprev, v, nullptr, nullptr, Jv, nullptr, s);
+  const double* base = F0;
+  if (!base) {
+    PF_TRY(launch_fg(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, pb->tmp_vec[0], nullptr, s));
+    base = pb->tmp_vec[0];
+  } else {
+    PF_TRY(check_vec(F0, "F0"));
+  }
+  PF_TRY(blas_fd_eps(pb, U, v, pb->n_dof, pb->eps_dev, s));
+  return launch_fg(pb, MODE_FD, U, Uprev, v, base, pb->eps_dev, Jv, nullptr, s);
+}
+
+int pf_fg_step(pf_problem* pb, const double* Uprev2, const double* Uprev, double* U,
+               const pf_solver_opts* opts, pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 2));
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(Uprev2, "Uprev2"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(U, "U"));
+  stats_reset(stats);
+  const double t0 = now_ms();
+  int rc = fg_step_impl(pb, Uprev2, Uprev, U, *opts, stats, S(stream));
+  if (stats) {
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
+}
+
+int pf_fg_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* opts,
+                 pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 2));
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(states, "states"));
+  if (steps < 0) {
+    set_error("steps must be >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = S(stream);
+  const long long n = pb->n_dof;
+  pf_solver_stats acc;
+  stats_reset(&acc);
+  const double tstart = now_ms();
+  for (int k = 0; k < steps; ++k) {
+    double* prev = states + (long long)k * n;
+    double* next = prev + n;
+    const double* prev2 = k > 0 ? prev - n : prev;
+    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    pf_solver_stats st;
+    stats_reset(&st);
+    int rc = fg_step_impl(pb, prev2, prev, next, *opts, &st, s);
     acc.newton_its += st.newton_its;
     acc.gmres_its_total += st.gmres_its_total;
     acc.backtracks += st.backtracks;

@@ -11,7 +11,7 @@
 // Gauss rule.  The analytic tangent evaluates the same pointwise function on
 // dual numbers (value, directional derivative): forward-mode differentiation
 // of exactly the residual's arithmetic.
-#include "pf_element.h"
+#include "pf_dual.h"
 
 namespace pf {
 
@@ -19,39 +19,6 @@ namespace {
 
 constexpr int kAlloyBlock = 128;
 constexpr double kInv2Sqrt2 = 0.35355339059327376220;  // 1/(2 sqrt 2)
-
-// 1/sqrt(x), x > 0: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = r * fma(-0.5 * x * r, r, 1.5);
-  return r * fma(-0.5 * x * r, r, 1.5);
-}
-
-// Dual number v + d eps (eps^2 = 0) for forward-mode derivatives.
-struct Dual {
-  double v, d;
-};
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
-__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
-__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
-__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
-
-__device__ __forceinline__ double rcp_t(double x) { return rcp_nr(x); }
-__device__ __forceinline__ Dual rcp_t(Dual x) {
-  const double r = rcp_nr(x.v);
-  return {r, -x.d * r * r};
-}
-__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt_nr(x); }
-__device__ __forceinline__ Dual rsqrt_t(Dual x) {
-  const double r = rsqrt_nr(x.v);
-  return {r, -0.5 * x.d * r * r * r};
-}
-__device__ __forceinline__ double val(double x) { return x; }
-__device__ __forceinline__ double val(Dual x) { return x.v; }
 
 // Pointwise terms of the alloy residual: s1, f1 (phi rows: value and flux
 // parts), s2, f2 (u rows).  hist = (1 - theta)(phi^n - phi^(n-1))/dt, x the
@@ -343,7 +310,7 @@ int alloy_explicit(pf_problem* pb, const double* Un, double t_n, double* E, hipS
   return blas_axpby(1.0 - th, E, 0.0, E, E, pb->n_dof, s);
 }
 
-int alloy_history(pf_problem* pb, const double* Un, const double* Unm1, hipStream_t s) {
+int history_rate(pf_problem* pb, const double* Un, const double* Unm1, hipStream_t s) {
   const long long n = pb->geo.n_nodes;
   long long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;

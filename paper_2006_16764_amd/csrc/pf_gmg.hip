@@ -834,13 +834,18 @@ hipError_t hier_free(Hier<T>& H) {
 
 // Mass and stiffness scales of the two blocks: phi block (1/dt) M_c +
 // theta K_c; u block (1/dt) M + theta D K (thermal) or (1+k)/(2 dt) M +
-// theta D K (alloy, the one-sided mobility at its liquid value).
+// theta D K (alloy, the one-sided mobility at its liquid value).  Free
+// growth: (1/dt) M_c + theta beta Gamma K_c and (1/dt) M + theta alpha K.
 void block_scales(const pf_problem* pb, double* sm, double* sk) {
   const double idt = 1.0 / pb->params.dt, th = pb->params.theta;
   sm[0] = idt;
   sk[0] = th;
   sm[1] = pb->model == 1 ? 0.5 * (1.0 + pb->alloy.k) * idt : idt;
   sk[1] = th * pb->params.D;
+  if (pb->model == 2) {
+    sk[0] = th * pb->fg.beta * pb->fg.Gamma;
+    sk[1] = th * pb->fg.alpha;
+  }
 }
 
 template <int DIM, class T>

@@ -61,6 +61,17 @@ struct AlloyConst {
   int use_hist;     // 0: the history rate is zero
 };
 
+// Free-growth constants of one element-kernel launch (host-computed).
+struct FgConst {
+  double bg;      // beta Gamma
+  double c_dw;    // beta Gamma / W^2 (double-well term)
+  double c_drv;   // 5 beta / W (driving-force term)
+  double Tm, alpha, Lcp;
+  double theta;   // time weight of this launch (1 for the explicit part)
+  int use_hist;   // 0: the history rate is zero
+  int n_macro[2]; // order 2: elements per axis; h_macro = 2 G.h
+};
+
 // Element-loop modes of the residual kernel family.
 // MODE_VJPU: (dF/dU)^T w only (the operator of the transposed Krylov solve).
 enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4 };
@@ -92,7 +103,16 @@ int launch_alloy(pf_problem* pb, int mode, const double* U, const double* Uprev,
                  const double* F0, const double* eps_dev, double* out0, double* coef,
                  hipStream_t s);
 int alloy_explicit(pf_problem* pb, const double* Un, double t_n, double* E, hipStream_t s);
-int alloy_history(pf_problem* pb, const double* Un, const double* Unm1, hipStream_t s);
+int history_rate(pf_problem* pb, const double* Un, const double* Unm1, hipStream_t s);
+
+// Free-growth model (pf_freegrowth.hip), orders 1 and 2: launch_fg modes RES,
+// FD, JVP with the history rate pb->hist; fg_explicit: spatial terms at U^n
+// scaled by 1 - theta.  Order-2 handles index nodes on the (2n+1)^dim grid
+// (pb->geo describes it as an order-1 grid of 2n cells per axis).
+int launch_fg(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
+              const double* F0, const double* eps_dev, double* out0, double* coef, hipStream_t s);
+int fg_explicit(pf_problem* pb, const double* Un, double* E, hipStream_t s);
+long long fg_elem_buf_len(const pf_problem* pb);
 
 // ----------------------------------------------------------------- BLAS-1 (pf_blas.hip)
 // Deterministic reductions over n doubles: fixed grid, fixed order.
@@ -170,8 +190,9 @@ struct pf_problem {
 
   // alloy model (pf_set_alloy): parameters, the history rate
   // (1 - theta)(phi^n - phi^(n-1))/dt per node, and the time of the implicit part
-  int model;             // 0 thermal, 1 alloy
+  int model;             // 0 thermal, 1 alloy, 2 free growth
   pf_alloy_params alloy;
+  pf_freegrowth_params fg;
   double* hist;          // n_nodes doubles
   double t_new;
 

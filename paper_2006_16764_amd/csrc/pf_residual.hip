@@ -219,6 +219,7 @@ int launch_residual_family(pf_problem* pb, int mode, const double* U, const doub
                            double* out0, double* out1, double* vjp_part, hipStream_t s,
                            double* coef) {
   if (pb->model == 1) return launch_alloy(pb, mode, U, Uprev, v, F0, eps_dev, out0, coef, s);
+  if (pb->model == 2) return launch_fg(pb, mode, U, Uprev, v, F0, eps_dev, out0, coef, s);
   if (pb->geo.dim == 3)
     return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
   return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);

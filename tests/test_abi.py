@@ -47,6 +47,7 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(pf_solver_opts), offsetof(pf_solver_opts, eta0), offsetof(pf_solver_opts, pc_precision));
   printf("%zu %zu %zu\\n", sizeof(pf_solver_stats), offsetof(pf_solver_stats, fnorm), offsetof(pf_solver_stats, t_total_ms));
   printf("%zu %zu\\n", sizeof(pf_alloy_params), offsetof(pf_alloy_params, v_pull));
+  printf("%zu %zu %zu\\n", offsetof(pf_params, order), sizeof(pf_freegrowth_params), offsetof(pf_freegrowth_params, Tm));
   return 0;
 }
 """)
@@ -57,7 +58,9 @@ int main(void) {
     expect = [ctypes.sizeof(P), P.dt.offset, P.delta2.offset, P.half_width.offset, P.theta.offset,
               ctypes.sizeof(O), O.eta0.offset, O.pc_precision.offset,
               ctypes.sizeof(S), S.fnorm.offset, S.t_total_ms.offset,
-              ctypes.sizeof(binding.pf_alloy_params), binding.pf_alloy_params.v_pull.offset]
+              ctypes.sizeof(binding.pf_alloy_params), binding.pf_alloy_params.v_pull.offset,
+              P.order.offset, ctypes.sizeof(binding.pf_freegrowth_params),
+              binding.pf_freegrowth_params.Tm.offset]
     assert [int(v) for v in out] == expect
 
 
