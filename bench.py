@@ -19,9 +19,11 @@ is for the element kernel of the residual family, timed live with HIP events
 on its stream.  After the timed region the same Newton step is repeated from
 the same state with the FP64 V-cycle for the mixed-vs-FP64 comparison, one
 Crank-Nicolson (theta = 1/2) step continues from the last two states, the
-CPU oracle is timed on a bounded slab of the same workload, and the alloy model
+CPU oracle is timed on a bounded slab of the same workload, the alloy model
 (directional solidification, 1024 x 256 x 256 elements, theta = 1/2,
-dt = 0.002) takes a warm-up and two timed steps on its own seeded state.
+dt = 0.002) takes a warm-up and two timed steps on its own seeded state, and
+the free-growth model takes Crank-Nicolson steps on the paper's 150^2 mesh
+with Q1 and Q2 elements (kernel throughput of Q2 on 2048^2 elements).
 """
 from __future__ import annotations
 
@@ -48,6 +50,8 @@ def parse():
     ap.add_argument("--alloy-workload", default="alloy3d_1024x256x256")
     ap.add_argument("--alloy-steps", type=int, default=2)
     ap.add_argument("--no-alloy", action="store_true")
+    ap.add_argument("--fg-steps", type=int, default=5)
+    ap.add_argument("--no-freegrowth", action="store_true")
     return ap.parse_args()
 
 
@@ -257,6 +261,11 @@ def main():
         torch.cuda.empty_cache()
         alloy = alloy_leg(a, binding, inputs, torch, dev, time_call, stream)
 
+    # ---- free-growth model, Q1 and Q2, at the paper's size and a throughput size
+    freegrowth = None
+    if not a.no_freegrowth:
+        freegrowth = freegrowth_leg(a, binding, inputs, torch, dev, time_call)
+
     out = {
         "metric": "Jv MDOF/s + JFNK step time, mixed vs FP64 at 256^3 hex; % HBM roofline",
         "value": round(value, 2),
@@ -288,6 +297,7 @@ def main():
         "theta_half_step": cn,
         "cpu_baseline": cpu,
         "alloy": alloy,
+        "freegrowth": freegrowth,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -340,6 +350,59 @@ def alloy_leg(a, binding, inputs, torch, dev, time_call, stream):
                              (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv))}}
     log("alloy leg done")
     pb.close()
+    return out
+
+
+def freegrowth_leg(a, binding, inputs, torch, dev, time_call):
+    """Crank-Nicolson steps of the free-growth model on the paper's 150^2 mesh
+    (Q1 and Q2) from the seeded quarter seed, and residual / Jv kernel
+    throughput of Q2 on a 2048^2-element box."""
+    out = {}
+    opts = binding.default_opts(pc=binding.PF_PC_GMG, pc_precision=binding.PF_FP32,
+                                jv_mode=binding.PF_JV_FD, tau_r=1e-6)
+    for name in ("freegrowth2d_150_q1", "freegrowth2d_150_q2"):
+        w = inputs.freegrowth_workload(name)
+        pb = binding.freegrowth_problem_for(w)
+        S0 = torch.from_numpy(inputs.freegrowth_initial_state(w).reshape(-1)).to(dev)
+        prev2, prev = S0, S0.clone()
+        nxt = pb.new_vector()
+        nxt.copy_(prev)
+        pb.pf_fg_step(prev2, prev, nxt, opts)  # warm-up: first step of the run
+        prev2, prev, nxt = prev, nxt, prev2
+        recs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.fg_steps):
+            nxt.copy_(prev)
+            recs.append(pb.pf_fg_step(prev2, prev, nxt, opts))
+            prev2, prev, nxt = prev, nxt, prev2
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / max(a.fg_steps, 1)
+        out[name] = {"unknowns": pb.n_dof, "elements": w.n_elems, "order": w.order, "dt": w.dt,
+                     "tau_r": 1e-6, "ms_per_step": round(ms, 2),
+                     "newton_its": [r["newton_its"] for r in recs],
+                     "gmres_its": [r["gmres_its_total"] for r in recs]}
+        pb.close()
+        log(f"{name} done")
+    w = inputs.freegrowth_workload("freegrowth2d_2048_q2")
+    pb = binding.freegrowth_problem_for(w)
+    n = pb.n_dof
+    U0 = torch.from_numpy(inputs.freegrowth_initial_state(w).reshape(-1)).to(dev)
+    rng = np.random.default_rng(41)
+    U = U0 + torch.from_numpy(1e-3 * rng.standard_normal(n)).to(dev)
+    v = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    F, J = pb.new_vector(), pb.new_vector()
+    reps = max(2, a.kernel_reps // 2)
+    t_res = time_call(lambda: pb.pf_fg_residual(U, U0, U0, F), reps)
+    t_fd = time_call(lambda: pb.pf_fg_jvp(U, U0, U0, v, J, mode=binding.PF_JV_FD, F0=F), reps)
+    t_jv = time_call(lambda: pb.pf_fg_jvp(U, U0, U0, v, J, mode=binding.PF_JV_ANALYTIC), reps)
+    out[w.name] = {"unknowns": n, "elements": w.n_elems, "order": 2,
+                   "kernels_ms": {"residual": round(t_res, 3), "fd_jv": round(t_fd, 3),
+                                  "analytic_jv": round(t_jv, 3)},
+                   "kernels_mdofs": {k: round(n / (x * 1e-3) / 1e6, 1) for k, x in
+                                     (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv))}}
+    pb.close()
+    log("free-growth throughput done")
     return out
 
 

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kAlloyBlock)
     for (int a = 0; a < NA; ++a) E[(long long)(o * NA + a) * G.n_elems + e] = out[o][a];
 }
 
-__global__ void k_alloy_hist(long long n, const double2* __restrict__ Un,
+__global__ void k_history(long long n, const double2* __restrict__ Un,
                              const double2* __restrict__ Unm1, double c, double* __restrict__ hist) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -315,7 +315,7 @@ int history_rate(pf_problem* pb, const double* Un, const double* Unm1, hipStream
   long long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   const unsigned nb = (unsigned)blocks;
-  hipLaunchKernelGGL(k_alloy_hist, dim3(nb), dim3(256), 0, s, n,
+  hipLaunchKernelGGL(k_history, dim3(nb), dim3(256), 0, s, n,
                      reinterpret_cast<const double2*>(Un), reinterpret_cast<const double2*>(Unm1),
                      (1.0 - pb->params.theta) / pb->params.dt, pb->hist);
   PF_HIP_CHECK(hipGetLastError());
