@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   __shared__ double cb[NO][4][kThreads];
 
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % T.ntx;
   const int ty = (tile / T.ntx) % T.nty;
   const int tz = tile / (T.ntx * T.nty);

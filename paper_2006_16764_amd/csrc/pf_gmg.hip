@@ -481,7 +481,10 @@ __global__ void __launch_bounds__(SBX * SBY)
   __shared__ T cs[2][SBY + 1][SBX + 1];
   const int tid = threadIdx.x;
   const int tx = tid % SBX, ty = tid / SBX;
-  const int x0 = blockIdx.x * SBX, y0 = blockIdx.y * SBY, z0 = blockIdx.z * kz;
+  // 1-D grid of tiles (x fastest), dealt to the XCDs in contiguous runs
+  const int ntx = (g.nn[0] + SBX - 1) / SBX, nty = (g.nn[1] + SBY - 1) / SBY;
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * SBX, y0 = ((tile / ntx) % nty) * SBY, z0 = (tile / (ntx * nty)) * kz;
   const int ix = x0 + tx, iy = y0 + ty;
   const bool inside = ix < g.nn[0] && iy < g.nn[1];
   const int zend = min(z0 + kz, g.nn[2]);
@@ -508,17 +511,69 @@ __global__ void __launch_bounds__(SBX * SBY)
       cs[slot][hy][hx] = v;
     }
   };
+  // Software pipeline: the halo values of the next planes are fetched into
+  // registers (at most 2 per thread each) while the current plane is computed,
+  // and stored to the LDS ring at the top of the next iteration.
+  constexpr int NX = ((SBX + 2) * (SBY + 2) + SBX * SBY - 1) / (SBX * SBY);
+  constexpr int NC = ((SBX + 1) * (SBY + 1) + SBX * SBY - 1) / (SBX * SBY);
+  T2 rx[NX];
+  T rc[NC];
+  auto fetch_x = [&](int z) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const int q = tid + j * SBX * SBY;
+      const int hx = q % (SBX + 2), hy = q / (SBX + 2);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+      rx[j].x = 0;
+      rx[j].y = 0;
+      if (q < (SBX + 2) * (SBY + 2) && z >= 0 && z < g.nn[2] && gx >= 0 && gx < g.nn[0] &&
+          gy >= 0 && gy < g.nn[1])
+        rx[j] = x[gx + (long long)g.nn[0] * (gy + (long long)g.nn[1] * z)];
+    }
+  };
+  auto store_x = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const int q = tid + j * SBX * SBY;
+      if (q < (SBX + 2) * (SBY + 2)) xs[slot][q / (SBX + 2)][q % (SBX + 2)] = rx[j];
+    }
+  };
+  auto fetch_c = [&](int zc) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int q = tid + j * SBX * SBY;
+      const int hx = q % (SBX + 1), hy = q / (SBX + 1);
+      const int cx = x0 - 1 + hx, cy = y0 - 1 + hy;
+      rc[j] = 0;
+      if (q < (SBX + 1) * (SBY + 1) && zc >= 0 && zc < g.n[2] && cx >= 0 && cx < g.n[0] &&
+          cy >= 0 && cy < g.n[1])
+        rc[j] = c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * zc)];
+    }
+  };
+  auto store_c = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int q = tid + j * SBX * SBY;
+      if (q < (SBX + 1) * (SBY + 1)) cs[slot][q / (SBX + 1)][q % (SBX + 1)] = rc[j];
+    }
+  };
   // ring slots: node plane z lives in slot (z - z0 + 1) % 3, cell plane zc in (zc - z0 + 1) & 1
   load_x(0, z0 - 1);
   load_x(1, z0);
   load_c(0, z0 - 1);
+  fetch_x(z0 + 1);
+  fetch_c(z0);
   for (int z = z0; z < zend; ++z) {
     const int k = z - z0;
     const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
     const int cm = k & 1, cp = cm ^ 1;
-    load_x(sp, z + 1);
-    load_c(cp, z);
+    store_x(sp);  // plane z + 1
+    store_c(cp);  // cell plane z
     __syncthreads();
+    if (z + 1 < zend) {
+      fetch_x(z + 2);
+      fetch_c(z + 1);
+    }
     if (inside) {
       T cc[2][2][2];
       bool ex[2], ey[2], ez[2];
@@ -895,7 +950,8 @@ inline int tiled_kz(const LvK& k) {
 
 inline dim3 tiled_grid(const LvK& k) {
   const int kz = tiled_kz(k);
-  return dim3((k.nn[0] + SBX - 1) / SBX, (k.nn[1] + SBY - 1) / SBY, (k.nn[2] + kz - 1) / kz);
+  return dim3((unsigned)(((k.nn[0] + SBX - 1) / SBX) * ((k.nn[1] + SBY - 1) / SBY) *
+                         ((k.nn[2] + kz - 1) / kz)));
 }
 
 template <int DIM, class T, int IN, int OUT>

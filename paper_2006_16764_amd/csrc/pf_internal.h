@@ -51,6 +51,22 @@ struct Geo {
 
 Geo make_geo(const pf_params& p);
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Tiled kernels map the hardware workgroup index i to the logical tile so
+// that each XCD runs a contiguous run of tiles: neighbours then share their
+// halo rows in one L2 instead of fetching them from HBM separately.  The
+// first 8 floor(T/8) indices are permuted, the remainder keeps its order.
+#ifndef PF_XCD_REMAP
+#define PF_XCD_REMAP 1
+#endif
+constexpr unsigned kNumXcd = 8;
+__device__ __forceinline__ unsigned xcd_tile(unsigned i, unsigned T) {
+  if (!PF_XCD_REMAP) return i;
+  const unsigned q = T / kNumXcd;
+  if (i >= kNumXcd * q) return i;
+  return (i % kNumXcd) * q + i / kNumXcd;
+}
+
 // Alloy-model constants of one element-kernel launch (host-computed).
 struct AlloyConst {
   double omk;       // 1 - k
