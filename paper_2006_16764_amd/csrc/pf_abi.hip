@@ -526,6 +526,50 @@ int fg_step_impl(pf_problem* pb, const double* Uprev2, const double* Uprev, doub
   return newton_impl(pb, Uprev, pb->params.theta == 1.0 ? nullptr : pb->load_vec, U, o, st, s);
 }
 
+// One thermal step (backward Euler, or theta < 1 with the explicit part).
+int thermal_step_impl(pf_problem* pb, const double* Uprev2, const double* Uprev, double* U,
+                      const pf_solver_opts& o, pf_solver_stats* st, hipStream_t s) {
+  if (pb->params.theta == 1.0) return newton_impl(pb, Uprev, nullptr, U, o, st, s);
+  PF_TRY(ensure_load_vec(pb));
+  PF_TRY(theta_explicit_impl(pb, Uprev, Uprev2, pb->load_vec, s));
+  return newton_impl(pb, Uprev, pb->load_vec, U, o, st, s);
+}
+
+// steps time steps over the checkpoint array states: step k goes from
+// states[k] (and states[k-1]; U^(-1) = U^0) to states[k+1], starting Newton
+// from a copy of states[k].  step(prev2, prev, k, next, stats) takes one step.
+template <class Step>
+int evolve_loop(pf_problem* pb, double* states, int steps, pf_solver_stats* stats, hipStream_t s,
+                Step step) {
+  const long long n = pb->n_dof;
+  pf_solver_stats acc;
+  stats_reset(&acc);
+  const double t0 = now_ms();
+  for (int k = 0; k < steps; ++k) {
+    double* prev = states + (long long)k * n;
+    double* next = prev + n;
+    const double* prev2 = k > 0 ? prev - n : prev;
+    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    pf_solver_stats st;
+    stats_reset(&st);
+    const int rc = step(prev2, prev, k, next, &st);
+    acc.newton_its += st.newton_its;
+    acc.gmres_its_total += st.gmres_its_total;
+    acc.backtracks += st.backtracks;
+    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
+    acc.f0 = st.f0;
+    acc.f_final = st.f_final;
+    if (rc != PF_OK) {
+      acc.status = rc;
+      if (stats) *stats = acc;
+      return rc;
+    }
+  }
+  acc.t_total_ms = now_ms() - t0;
+  if (stats) *stats = acc;
+  return PF_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -896,18 +940,10 @@ int pf_newton_step_theta(pf_problem* pb, const double* Uprev2, const double* Upr
   PF_TRY(check_opts(pb, opts));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
-  const bool weighted = pb->params.theta != 1.0;
-  if (weighted) {
-    PF_TRY(check_vec(Uprev2, "Uprev2"));
-    PF_TRY(ensure_load_vec(pb));
-  }
+  if (pb->params.theta != 1.0) PF_TRY(check_vec(Uprev2, "Uprev2"));
   stats_reset(stats);
   const double t0 = now_ms();
-  hipStream_t s = S(stream);
-  int rc = PF_OK;
-  if (weighted) rc = theta_explicit_impl(pb, Uprev, Uprev2, pb->load_vec, s);
-  if (rc == PF_OK)
-    rc = newton_impl(pb, Uprev, weighted ? pb->load_vec : nullptr, U, *opts, stats, s);
+  const int rc = thermal_step_impl(pb, Uprev2, Uprev, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;
     stats->t_total_ms = now_ms() - t0;
@@ -944,36 +980,11 @@ int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* o
     return PF_ERR_INVALID_ARG;
   }
   hipStream_t s = S(stream);
-  const long long n = pb->n_dof;
-  pf_solver_stats acc;
-  stats_reset(&acc);
-  const double t0 = now_ms();
-  const bool weighted = pb->params.theta != 1.0;
-  if (weighted) PF_TRY(ensure_load_vec(pb));
-  for (int k = 0; k < steps; ++k) {
-    double* prev = states + (long long)k * n;
-    double* next = prev + n;
-    const double* prev2 = k > 0 ? prev - n : prev;  // U^(-1) = U^0
-    if (weighted) PF_TRY(theta_explicit_impl(pb, prev, prev2, pb->load_vec, s));
-    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    pf_solver_stats st;
-    stats_reset(&st);
-    int rc = newton_impl(pb, prev, weighted ? pb->load_vec : nullptr, next, *opts, &st, s);
-    acc.newton_its += st.newton_its;
-    acc.gmres_its_total += st.gmres_its_total;
-    acc.backtracks += st.backtracks;
-    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
-    acc.f0 = st.f0;
-    acc.f_final = st.f_final;
-    if (rc != PF_OK) {
-      acc.status = rc;
-      if (stats) *stats = acc;
-      return rc;
-    }
-  }
-  acc.t_total_ms = now_ms() - t0;
-  if (stats) *stats = acc;
-  return PF_OK;
+  return evolve_loop(pb, states, steps, stats, s,
+                     [&](const double* prev2, const double* prev, int, double* next,
+                         pf_solver_stats* st) {
+                       return thermal_step_impl(pb, prev2, prev, next, *opts, st, s);
+                     });
 }
 
 int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const double* mu,
@@ -1167,33 +1178,12 @@ int pf_alloy_evolve(pf_problem* pb, double* states, int steps, double t0,
     return PF_ERR_INVALID_ARG;
   }
   hipStream_t s = S(stream);
-  const long long n = pb->n_dof;
-  pf_solver_stats acc;
-  stats_reset(&acc);
-  const double tstart = now_ms();
-  for (int k = 0; k < steps; ++k) {
-    double* prev = states + (long long)k * n;
-    double* next = prev + n;
-    const double* prev2 = k > 0 ? prev - n : prev;
-    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    pf_solver_stats st;
-    stats_reset(&st);
-    int rc = alloy_step_impl(pb, prev2, prev, t0 + k * pb->params.dt, next, *opts, &st, s);
-    acc.newton_its += st.newton_its;
-    acc.gmres_its_total += st.gmres_its_total;
-    acc.backtracks += st.backtracks;
-    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
-    acc.f0 = st.f0;
-    acc.f_final = st.f_final;
-    if (rc != PF_OK) {
-      acc.status = rc;
-      if (stats) *stats = acc;
-      return rc;
-    }
-  }
-  acc.t_total_ms = now_ms() - tstart;
-  if (stats) *stats = acc;
-  return PF_OK;
+  return evolve_loop(pb, states, steps, stats, s,
+                     [&](const double* prev2, const double* prev, int k, double* next,
+                         pf_solver_stats* st) {
+                       return alloy_step_impl(pb, prev2, prev, t0 + k * pb->params.dt, next,
+                                              *opts, st, s);
+                     });
 }
 
 int pf_set_freegrowth(pf_problem* pb, const pf_freegrowth_params* f) {
@@ -1331,33 +1321,11 @@ int pf_fg_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts
     return PF_ERR_INVALID_ARG;
   }
   hipStream_t s = S(stream);
-  const long long n = pb->n_dof;
-  pf_solver_stats acc;
-  stats_reset(&acc);
-  const double tstart = now_ms();
-  for (int k = 0; k < steps; ++k) {
-    double* prev = states + (long long)k * n;
-    double* next = prev + n;
-    const double* prev2 = k > 0 ? prev - n : prev;
-    PF_HIP_CHECK(hipMemcpyAsync(next, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    pf_solver_stats st;
-    stats_reset(&st);
-    int rc = fg_step_impl(pb, prev2, prev, next, *opts, &st, s);
-    acc.newton_its += st.newton_its;
-    acc.gmres_its_total += st.gmres_its_total;
-    acc.backtracks += st.backtracks;
-    if (k < PF_MAX_LOG) acc.gmres_its[k] = st.gmres_its_total;
-    acc.f0 = st.f0;
-    acc.f_final = st.f_final;
-    if (rc != PF_OK) {
-      acc.status = rc;
-      if (stats) *stats = acc;
-      return rc;
-    }
-  }
-  acc.t_total_ms = now_ms() - tstart;
-  if (stats) *stats = acc;
-  return PF_OK;
+  return evolve_loop(pb, states, steps, stats, s,
+                     [&](const double* prev2, const double* prev, int, double* next,
+                         pf_solver_stats* st) {
+                       return fg_step_impl(pb, prev2, prev, next, *opts, st, s);
+                     });
 }
 
 int pf_misfit(pf_problem* pb, const double* U, const double* phi_target, double* L_dev,
