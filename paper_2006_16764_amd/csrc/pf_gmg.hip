@@ -314,12 +314,18 @@ __global__ void k_coarsen(LvK fg, LvK cg, const T* __restrict__ cf, T* __restric
   cc[E] = acc * (T)(DIM == 3 ? 0.125 : 0.25);
 }
 
+// Chebyshev step flags.  kWriteD: store the step's direction d (only a next
+// step that reads it needs it).  kReadD: read the previous direction from d
+// (a step whose alpha is 0, the first one, needs none).  kDIsX: the previous
+// step started from x = 0, so its direction equals its iterate x_in.
+constexpr int kWriteD = 1, kReadD = 2, kDIsX = 4;
+
 // One Jacobi-Chebyshev step for both blocks:
 //   d = alpha d + beta D^-1 (b - A x_in),  x_out = x_in + d.
 // IN: 0 zero start (x_in = 0, b from the level array); 1 zero start with b
 // read from the FP64 interleaved r64 and stored into b; 2 general step.
 // OUT: 0 writes x_out; 1 writes the FP64 interleaved z64 (last step).
-template <int DIM, class T, int IN, int OUT>
+template <int DIM, class T, int IN, int OUT, int FL>
 __global__ void __launch_bounds__(kT)
     k_smooth(LvK g, const T* __restrict__ c, typename V2<T>::type* __restrict__ b,
              const typename V2<T>::type* __restrict__ x_in, typename V2<T>::type* __restrict__ x_out,
@@ -347,7 +353,9 @@ __global__ void __launch_bounds__(kT)
     const auto xv = x_in[i];
     xi0 = xv.x;
     xi1 = xv.y;
-    const auto dv = d[i];
+    typename V2<T>::type dv = xv;
+    if (FL & kReadD) dv = d[i];
+    if (!(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
     dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
     dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
   } else {
@@ -361,7 +369,7 @@ __global__ void __launch_bounds__(kT)
   if (OUT == 1) {
     z64[i] = make_double2((double)(xi0 + dn0), (double)(xi1 + dn1));
   } else {
-    d[i] = dn;
+    if (FL & kWriteD) d[i] = dn;
     typename V2<T>::type xo;
     xo.x = xi0 + dn0;
     xo.y = xi1 + dn1;
@@ -470,7 +478,7 @@ constexpr long long kTiledMinGroups = PF_TILED_MIN_GROUPS;
 
 // OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
 // writing the FP64 interleaved z64 (last step of the V-cycle).
-template <class T, int OP>
+template <class T, int OP, int FL>
 __global__ void __launch_bounds__(SBX * SBY)
     k_stencil3(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
                const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ out,
@@ -615,7 +623,9 @@ __global__ void __launch_bounds__(SBX * SBY)
         out[i] = o;
       } else {
         const T2 xi = xs[s0][ty + 1][tx + 1];
-        const T2 dv = d[i];
+        T2 dv = xi;
+        if (FL & kReadD) dv = d[i];
+        if (!(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
         const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / w0[13];
         const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / w1[13];
         if (OP == 2) {
@@ -626,7 +636,7 @@ __global__ void __launch_bounds__(SBX * SBY)
           dn.y = dn1;
           xo.x = xi.x + dn0;
           xo.y = xi.y + dn1;
-          d[i] = dn;
+          if (FL & kWriteD) d[i] = dn;
           out[i] = xo;
         }
       }
@@ -954,20 +964,20 @@ inline dim3 tiled_grid(const LvK& k) {
                          ((k.nn[2] + kz - 1) / kz)));
 }
 
-template <int DIM, class T, int IN, int OUT>
+template <int DIM, class T, int IN, int OUT, int FL>
 int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::type* x_out,
                 const double* al, const double* be, int k, const double* r64, double* z64,
                 hipStream_t s) {
   if (IN == 2 && use_tiled(L.k, DIM)) {
     constexpr int OP = OUT == 1 ? 2 : 1;
-    hipLaunchKernelGGL((k_stencil3<T, OP>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+    hipLaunchKernelGGL((k_stencil3<T, OP, FL>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b, x_in, x_out, L.d,
                        (T)al[2 * k], (T)al[2 * k + 1], (T)be[2 * k], (T)be[2 * k + 1],
                        reinterpret_cast<double2*>(z64), tiled_kz(L.k));
     PF_HIP_CHECK(hipGetLastError());
     return PF_OK;
   }
-  hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+  hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT, FL>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
                      (const T*)L.c, L.b, x_in, x_out, L.d, (T)al[2 * k], (T)al[2 * k + 1],
                      (T)be[2 * k], (T)be[2 * k + 1], reinterpret_cast<const double2*>(r64),
                      reinterpret_cast<double2*>(z64));
@@ -1018,11 +1028,12 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
         be[2 * k + 1] = co[4 * k + 3];
       }
       // ping-pong ending in xb (kCoarseDegree is even)
-      PF_TRY((smooth_step<DIM, T, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
+      PF_TRY((smooth_step<DIM, T, 0, 0, kWriteD>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
       for (int k = 1; k < kCoarseDegree; ++k) {
         auto* in = (k & 1) ? L.xa : L.xb;
         auto* out = (k & 1) ? L.xb : L.xa;
-        PF_TRY((smooth_step<DIM, T, 2, 0>(L, in, out, al, be, k, nullptr, nullptr, s)));
+        PF_TRY((smooth_step<DIM, T, 2, 0, kReadD | kWriteD>(L, in, out, al, be, k, nullptr, nullptr,
+                                                            s)));
       }
     }
     if (top) {
@@ -1035,12 +1046,13 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   }
   double al[4], be[4];
   smoother_coefs(L, al, be);
-  // pre-smoothing from zero: xa, then xb
-  if (top) PF_TRY((smooth_step<DIM, T, 1, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
-  else PF_TRY((smooth_step<DIM, T, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
-  PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
+  // pre-smoothing from zero: xa, then xb.  The first direction equals xa, and
+  // the post-smoothing restarts with alpha = 0: neither step stores d.
+  if (top) PF_TRY((smooth_step<DIM, T, 1, 0, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
+  else PF_TRY((smooth_step<DIM, T, 0, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
+  PF_TRY((smooth_step<DIM, T, 2, 0, kDIsX>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
   if (use_tiled(L.k, DIM)) {
-    hipLaunchKernelGGL((k_stencil3<T, 0>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+    hipLaunchKernelGGL((k_stencil3<T, 0, 0>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,
                        (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
                        nullptr, tiled_kz(L.k));
@@ -1058,10 +1070,11 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   hipLaunchKernelGGL((k_prolong_add<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
                      (const typename V2<T>::type*)C.xb, L.xb);
   PF_HIP_CHECK(hipGetLastError());
-  // post-smoothing from the corrected iterate: xb -> xa -> xb (or z64)
-  PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xb, L.xa, al, be, 0, nullptr, nullptr, s)));
-  if (top) PF_TRY((smooth_step<DIM, T, 2, 1>(L, L.xa, nullptr, al, be, 1, nullptr, z64, s)));
-  else PF_TRY((smooth_step<DIM, T, 2, 0>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
+  // post-smoothing from the corrected iterate: xb -> xa -> xb (or z64); only
+  // the first step's direction is read again
+  PF_TRY((smooth_step<DIM, T, 2, 0, kWriteD>(L, L.xb, L.xa, al, be, 0, nullptr, nullptr, s)));
+  if (top) PF_TRY((smooth_step<DIM, T, 2, 1, kReadD>(L, L.xa, nullptr, al, be, 1, nullptr, z64, s)));
+  else PF_TRY((smooth_step<DIM, T, 2, 0, kReadD>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
   return PF_OK;
 }
 
