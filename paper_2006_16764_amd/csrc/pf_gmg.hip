@@ -23,6 +23,7 @@
 // the d = 0 weight, so no diagonal array is stored.  Both blocks are processed
 // by the same thread and stored as interleaved (phi, u) pairs.
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "pf_element.h"
@@ -68,6 +69,7 @@ struct Level {
   typename V2<T>::type* b;       // right-hand side
   typename V2<T>::type* r;       // residual
   typename V2<T>::type* d;       // Chebyshev direction
+  int kz;                        // z-march length of the tiled 3-D stencils (0: untiled)
 };
 
 template <class T>
@@ -476,6 +478,30 @@ constexpr int SBX = 32, SBY = 8, SKZ = 32;
 #endif
 constexpr long long kTiledMinGroups = PF_TILED_MIN_GROUPS;
 
+inline bool use_tiled(const LvK& k, int dim) { return dim == 3 && k.nn[0] >= SBX && k.nn[1] >= SBY; }
+
+// z-march length: the longest power of two up to SKZ that still gives at
+// least min_groups workgroups
+inline int tiled_kz(const LvK& k, long long min_groups) {
+  const long long tiles = (long long)((k.nn[0] + SBX - 1) / SBX) * ((k.nn[1] + SBY - 1) / SBY);
+  int kz = SKZ;
+  while (kz > 1 && tiles * ((k.nn[2] + kz - 1) / kz) < min_groups) kz /= 2;
+  return kz;
+}
+
+// The workgroup target of the z-march choice; the environment variable
+// PF_GMG_TILE_GROUPS (a positive integer, read when the hierarchy is built)
+// overrides it, which lets small meshes exercise long z-marches.
+inline long long tiled_min_groups() {
+  const char* e = std::getenv("PF_GMG_TILE_GROUPS");
+  if (e && *e) {
+    char* end = nullptr;
+    const long long v = std::strtoll(e, &end, 10);
+    if (end && *end == '\0' && v > 0) return v;
+  }
+  return kTiledMinGroups;
+}
+
 // OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
 // writing the FP64 interleaved z64 (last step of the V-cycle).
 template <class T, int OP, int FL>
@@ -497,80 +523,76 @@ __global__ void __launch_bounds__(SBX * SBY)
   const bool inside = ix < g.nn[0] && iy < g.nn[1];
   const int zend = min(z0 + kz, g.nn[2]);
 
-  auto load_x = [&](int slot, int z) {
-    for (int q = tid; q < (SBX + 2) * (SBY + 2); q += SBX * SBY) {
-      const int hx = q % (SBX + 2), hy = q / (SBX + 2);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
-      T2 v;
-      v.x = 0;
-      v.y = 0;
-      if (z >= 0 && z < g.nn[2] && gx >= 0 && gx < g.nn[0] && gy >= 0 && gy < g.nn[1])
-        v = x[gx + (long long)g.nn[0] * (gy + (long long)g.nn[1] * z)];
-      xs[slot][hy][hx] = v;
-    }
-  };
-  auto load_c = [&](int slot, int zc) {
-    for (int q = tid; q < (SBX + 1) * (SBY + 1); q += SBX * SBY) {
-      const int hx = q % (SBX + 1), hy = q / (SBX + 1);
-      const int cx = x0 - 1 + hx, cy = y0 - 1 + hy;
-      T v = 0;
-      if (zc >= 0 && zc < g.n[2] && cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1])
-        v = c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * zc)];
-      cs[slot][hy][hx] = v;
-    }
-  };
   // Software pipeline: the halo values of the next planes are fetched into
   // registers (at most 2 per thread each) while the current plane is computed,
-  // and stored to the LDS ring at the top of the next iteration.
-  constexpr int NX = ((SBX + 2) * (SBY + 2) + SBX * SBY - 1) / (SBX * SBY);
-  constexpr int NC = ((SBX + 1) * (SBY + 1) + SBX * SBY - 1) / (SBX * SBY);
+  // and stored to the LDS ring at the top of the next iteration.  Each thread's
+  // halo slots q = tid + j * 256 and their in-plane offsets do not change with z.
+  constexpr int NQX = (SBX + 2) * (SBY + 2), NQC = (SBX + 1) * (SBY + 1);
+  constexpr int NX = (NQX + SBX * SBY - 1) / (SBX * SBY);
+  constexpr int NC = (NQC + SBX * SBY - 1) / (SBX * SBY);
+  const long long plane_n = (long long)g.nn[0] * g.nn[1];
+  const long long plane_c = (long long)g.n[0] * g.n[1];
+  int offx[NX], offc[NC];
+  bool okx[NX], okc[NC];
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    const int q = tid + j * SBX * SBY;
+    const int gx = x0 - 1 + q % (SBX + 2), gy = y0 - 1 + q / (SBX + 2);
+    okx[j] = q < NQX && gx >= 0 && gx < g.nn[0] && gy >= 0 && gy < g.nn[1];
+    offx[j] = okx[j] ? gx + g.nn[0] * gy : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int q = tid + j * SBX * SBY;
+    const int cx = x0 - 1 + q % (SBX + 1), cy = y0 - 1 + q / (SBX + 1);
+    okc[j] = q < NQC && cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1];
+    offc[j] = okc[j] ? cx + g.n[0] * cy : 0;
+  }
   T2 rx[NX];
   T rc[NC];
   auto fetch_x = [&](int z) {
+    const bool zin = z >= 0 && z < g.nn[2];
+    const T2* xp = x + plane_n * (zin ? z : 0);
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      const int q = tid + j * SBX * SBY;
-      const int hx = q % (SBX + 2), hy = q / (SBX + 2);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
       rx[j].x = 0;
       rx[j].y = 0;
-      if (q < (SBX + 2) * (SBY + 2) && z >= 0 && z < g.nn[2] && gx >= 0 && gx < g.nn[0] &&
-          gy >= 0 && gy < g.nn[1])
-        rx[j] = x[gx + (long long)g.nn[0] * (gy + (long long)g.nn[1] * z)];
+      if (zin && okx[j]) rx[j] = xp[offx[j]];
     }
   };
   auto store_x = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const int q = tid + j * SBX * SBY;
-      if (q < (SBX + 2) * (SBY + 2)) xs[slot][q / (SBX + 2)][q % (SBX + 2)] = rx[j];
+      if (q < NQX) (&xs[slot][0][0])[q] = rx[j];
     }
   };
   auto fetch_c = [&](int zc) {
+    const bool zin = zc >= 0 && zc < g.n[2];
+    const T* cpl = c + plane_c * (zin ? zc : 0);
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const int q = tid + j * SBX * SBY;
-      const int hx = q % (SBX + 1), hy = q / (SBX + 1);
-      const int cx = x0 - 1 + hx, cy = y0 - 1 + hy;
       rc[j] = 0;
-      if (q < (SBX + 1) * (SBY + 1) && zc >= 0 && zc < g.n[2] && cx >= 0 && cx < g.n[0] &&
-          cy >= 0 && cy < g.n[1])
-        rc[j] = c[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * zc)];
+      if (zin && okc[j]) rc[j] = cpl[offc[j]];
     }
   };
   auto store_c = [&](int slot) {
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
       const int q = tid + j * SBX * SBY;
-      if (q < (SBX + 1) * (SBY + 1)) cs[slot][q / (SBX + 1)][q % (SBX + 1)] = rc[j];
+      if (q < NQC) (&cs[slot][0][0])[q] = rc[j];
     }
   };
   // ring slots: node plane z lives in slot (z - z0 + 1) % 3, cell plane zc in (zc - z0 + 1) & 1
-  load_x(0, z0 - 1);
-  load_x(1, z0);
-  load_c(0, z0 - 1);
+  fetch_x(z0 - 1);
+  store_x(0);
+  fetch_x(z0);
+  store_x(1);
+  fetch_c(z0 - 1);
+  store_c(0);
   fetch_x(z0 + 1);
   fetch_c(z0);
+  const long long ibase = ix + (long long)g.nn[0] * iy;
   for (int z = z0; z < zend; ++z) {
     const int k = z - z0;
     const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
@@ -583,14 +605,16 @@ __global__ void __launch_bounds__(SBX * SBY)
       fetch_c(z + 1);
     }
     if (inside) {
-      T cc[2][2][2];
-      bool ex[2], ey[2], ez[2];
-      ex[0] = ix - 1 >= 0;
-      ex[1] = ix < g.n[0];
-      ey[0] = iy - 1 >= 0;
-      ey[1] = iy < g.n[1];
-      ez[0] = z - 1 >= 0;
-      ez[1] = z < g.n[2];
+      // y = A x for both blocks, grouped by the corner-difference pattern p
+      // of the stencil offset (bit 0: x offset, 1: y, 2: z):
+      //   y0 = sum_p Ae0[p] sum_{t in p} s_t x0_t, s_t the sum of the cell
+      //        coefficients shared by the node and node t (cells outside the
+      //        mesh are staged as 0, so missing neighbours drop out);
+      //   y1 = sum_p Ae1[p] f_p sum_{t in p} x1_t, f_p the product over the
+      //        axes not in p of the number of cells along that axis (1 or 2);
+      //        along the axes in p the count is 0 or 1 and the neighbour value
+      //        is staged as 0 exactly when it is 0.
+      T cc[2][2][2];  // [bz][by][bx]
 #pragma unroll
       for (int by = 0; by < 2; ++by)
 #pragma unroll
@@ -598,22 +622,94 @@ __global__ void __launch_bounds__(SBX * SBY)
           cc[0][by][bx] = cs[cm][ty + by][tx + bx];
           cc[1][by][bx] = cs[cp][ty + by][tx + bx];
         }
-      T w0[27], w1[27];
-      stencil_weights<3, T>(g, cc, ex, ey, ez, w0, w1);
-      T y0 = 0, y1 = 0;
+      T Sz[2][2], Sy[2][2], Sx[2][2];  // pair sums along z, y, x
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          Sz[u][v] = cc[0][u][v] + cc[1][u][v];  // [by][bx]
+          Sy[u][v] = cc[u][0][v] + cc[u][1][v];  // [bz][bx]
+          Sx[u][v] = cc[u][v][0] + cc[u][v][1];  // [bz][by]
+        }
+      T Syz[2], Sxz[2], Sxy[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        Syz[u] = Sz[0][u] + Sz[1][u];  // [bx]
+        Sxz[u] = Sz[u][0] + Sz[u][1];  // [by]
+        Sxy[u] = Sx[u][0] + Sx[u][1];  // [bz]
+      }
+      const T Sall = Syz[0] + Syz[1];
       const int sl[3] = {sm, s0, sp};
+      auto X = [&](int dx, int dy, int dz) { return xs[sl[dz]][ty + dy][tx + dx]; };
+      // phi block, per pattern
+      T P0[8];
+      P0[0] = Sall * X(1, 1, 1).x;
+      P0[1] = Syz[0] * X(0, 1, 1).x + Syz[1] * X(2, 1, 1).x;
+      P0[2] = Sxz[0] * X(1, 0, 1).x + Sxz[1] * X(1, 2, 1).x;
+      P0[4] = Sxy[0] * X(1, 1, 0).x + Sxy[1] * X(1, 1, 2).x;
+      P0[3] = 0;
+      P0[5] = 0;
+      P0[6] = 0;
+      P0[7] = 0;
 #pragma unroll
-      for (int tz = 0; tz < 3; ++tz)
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int tyy = 0; tyy < 3; ++tyy)
+        for (int v = 0; v < 2; ++v) {
+          P0[3] += Sz[u][v] * X(2 * v, 2 * u, 1).x;  // [by][bx]
+          P0[5] += Sy[u][v] * X(2 * v, 1, 2 * u).x;  // [bz][bx]
+          P0[6] += Sx[u][v] * X(1, 2 * v, 2 * u).x;  // [bz][by]
 #pragma unroll
-          for (int txx = 0; txx < 3; ++txx) {
-            const T2 v = xs[sl[tz]][ty + tyy][tx + txx];
-            const int t = txx + 3 * tyy + 9 * tz;
-            y0 += w0[t] * v.x;
-            y1 += w1[t] * v.y;
-          }
-      const long long i = ix + (long long)g.nn[0] * (iy + (long long)g.nn[1] * z);
+          for (int w = 0; w < 2; ++w) P0[7] += cc[u][v][w] * X(2 * w, 2 * v, 2 * u).x;
+        }
+      // u block: sums over x first, then y, then z
+      T Xo[3][3], Xc[3][3];  // [dy][dz]
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          Xo[dy][dz] = X(0, dy, dz).y + X(2, dy, dz).y;
+          Xc[dy][dz] = X(1, dy, dz).y;
+        }
+      T G1[8];
+      {
+        T Yoo[3], Yoc[3], Yco[3], Ycc[3];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+          Yoo[dz] = Xo[0][dz] + Xo[2][dz];
+          Yoc[dz] = Xo[1][dz];
+          Yco[dz] = Xc[0][dz] + Xc[2][dz];
+          Ycc[dz] = Xc[1][dz];
+        }
+        G1[0] = Ycc[1];
+        G1[1] = Yoc[1];
+        G1[2] = Yco[1];
+        G1[3] = Yoo[1];
+        G1[4] = Ycc[0] + Ycc[2];
+        G1[5] = Yoc[0] + Yoc[2];
+        G1[6] = Yco[0] + Yco[2];
+        G1[7] = Yoo[0] + Yoo[2];
+      }
+      const T cx = (T)((ix - 1 >= 0 ? 1 : 0) + (ix < g.n[0] ? 1 : 0));
+      const T cy = (T)((iy - 1 >= 0 ? 1 : 0) + (iy < g.n[1] ? 1 : 0));
+      const T cz = (T)((z - 1 >= 0 ? 1 : 0) + (z < g.n[2] ? 1 : 0));
+      const T cxy = cx * cy;
+      T f[8];
+      f[0] = cxy * cz;
+      f[1] = cy * cz;
+      f[2] = cx * cz;
+      f[3] = cz;
+      f[4] = cxy;
+      f[5] = cy;
+      f[6] = cx;
+      f[7] = 1;
+      T y0 = 0, y1 = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        y0 += (T)g.Ae[0][q] * P0[q];
+        y1 += ((T)g.Ae[1][q] * f[q]) * G1[q];
+      }
+      const T dg0 = (T)g.Ae[0][0] * Sall, dg1 = (T)g.Ae[1][0] * f[0];
+      const long long i = ibase + plane_n * z;
       const T2 bb = b[i];
       const T r0 = bb.x - y0, r1 = bb.y - y1;
       if (OP == 0) {
@@ -626,8 +722,8 @@ __global__ void __launch_bounds__(SBX * SBY)
         T2 dv = xi;
         if (FL & kReadD) dv = d[i];
         if (!(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
-        const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / w0[13];
-        const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / w1[13];
+        const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
+        const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
         if (OP == 2) {
           z64[i] = make_double2((double)(xi.x + dn0), (double)(xi.y + dn1));
         } else {
@@ -843,6 +939,7 @@ int hier_alloc(pf_problem* pb, Hier<T>& H) {
   const Geo& G = pb->geo;
   int n[3] = {G.n[0], G.n[1], G.dim == 3 ? G.n[2] : 1};
   double h[3] = {G.h[0], G.h[1], G.h[2]};
+  const long long min_groups = tiled_min_groups();
   H.lv.clear();
   while (true) {
     Level<T> L{};
@@ -853,12 +950,15 @@ int hier_alloc(pf_problem* pb, Hier<T>& H) {
     }
     L.k.nnodes = (long long)L.k.nn[0] * L.k.nn[1] * L.k.nn[2];
     L.k.ncells = (long long)L.k.n[0] * L.k.n[1] * L.k.n[2];
+    L.kz = use_tiled(L.k, G.dim) ? tiled_kz(L.k, min_groups) : 0;
     const size_t nb = (size_t)L.k.nnodes * sizeof(typename V2<T>::type);
-    if (hipMalloc(&L.c, (size_t)L.k.ncells * sizeof(T)) != hipSuccess) return PF_ERR_OOM;
-    typename V2<T>::type** bufs[] = {&L.xa, &L.xb, &L.b, &L.r, &L.d};
+    // registered before allocating, so that hier_free releases a partial level
+    H.lv.push_back(L);
+    Level<T>& M = H.lv.back();
+    if (hipMalloc(&M.c, (size_t)M.k.ncells * sizeof(T)) != hipSuccess) return PF_ERR_OOM;
+    typename V2<T>::type** bufs[] = {&M.xa, &M.xb, &M.b, &M.r, &M.d};
     for (auto p : bufs)
       if (hipMalloc(p, nb) != hipSuccess) return PF_ERR_OOM;
-    H.lv.push_back(L);
     bool even = true;
     int mn = 1 << 30;
     for (int k = 0; k < G.dim; ++k) {
@@ -947,33 +1047,23 @@ int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) 
 }
 
 // Levels whose x rows span at least one tile use the 2.5-D kernels.
-inline bool use_tiled(const LvK& k, int dim) { return dim == 3 && k.nn[0] >= SBX && k.nn[1] >= SBY; }
-
-// z-march length: the longest power of two up to SKZ that still gives at
-// least kTiledMinGroups workgroups
-inline int tiled_kz(const LvK& k) {
-  const long long tiles = (long long)((k.nn[0] + SBX - 1) / SBX) * ((k.nn[1] + SBY - 1) / SBY);
-  int kz = SKZ;
-  while (kz > 1 && tiles * ((k.nn[2] + kz - 1) / kz) < kTiledMinGroups) kz /= 2;
-  return kz;
-}
-
-inline dim3 tiled_grid(const LvK& k) {
-  const int kz = tiled_kz(k);
+template <class T>
+inline dim3 tiled_grid(const Level<T>& L) {
+  const LvK& k = L.k;
   return dim3((unsigned)(((k.nn[0] + SBX - 1) / SBX) * ((k.nn[1] + SBY - 1) / SBY) *
-                         ((k.nn[2] + kz - 1) / kz)));
+                         ((k.nn[2] + L.kz - 1) / L.kz)));
 }
 
 template <int DIM, class T, int IN, int OUT, int FL>
 int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::type* x_out,
                 const double* al, const double* be, int k, const double* r64, double* z64,
                 hipStream_t s) {
-  if (IN == 2 && use_tiled(L.k, DIM)) {
+  if (IN == 2 && L.kz > 0) {
     constexpr int OP = OUT == 1 ? 2 : 1;
-    hipLaunchKernelGGL((k_stencil3<T, OP, FL>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+    hipLaunchKernelGGL((k_stencil3<T, OP, FL>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b, x_in, x_out, L.d,
                        (T)al[2 * k], (T)al[2 * k + 1], (T)be[2 * k], (T)be[2 * k + 1],
-                       reinterpret_cast<double2*>(z64), tiled_kz(L.k));
+                       reinterpret_cast<double2*>(z64), L.kz);
     PF_HIP_CHECK(hipGetLastError());
     return PF_OK;
   }
@@ -1051,11 +1141,11 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   if (top) PF_TRY((smooth_step<DIM, T, 1, 0, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
   else PF_TRY((smooth_step<DIM, T, 0, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
   PF_TRY((smooth_step<DIM, T, 2, 0, kDIsX>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
-  if (use_tiled(L.k, DIM)) {
-    hipLaunchKernelGGL((k_stencil3<T, 0, 0>), tiled_grid(L.k), dim3(SBX * SBY), 0, s, L.k,
+  if (L.kz > 0) {
+    hipLaunchKernelGGL((k_stencil3<T, 0, 0>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,
                        (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
-                       nullptr, tiled_kz(L.k));
+                       nullptr, L.kz);
   } else {
     hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,

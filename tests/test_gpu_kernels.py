@@ -186,6 +186,38 @@ def test_gmg_vcycle_parity(case, precision):
     assert rel(host(z), ref) < (1e-12 if precision == "fp64" else 2e-5)
 
 
+# 3-D meshes wide enough for the tiled 2.5-D smoother kernels on the finest two
+# levels (32 x 8 node tiles with ragged last tiles in x and y).  The workgroup
+# target of the z-march choice is lowered so that the same small meshes also run
+# long z-marches (kz = 32 over fewer planes than that, and kz = 2, 4) as the
+# 256^3 levels do; None keeps the default (kz = 1 at these sizes).
+TILED_PC_CASES = [
+    (3, (64, 16, 16), (25.6, 6.4, 6.4), 0.2, 0.05, 1.6, 2.0),
+    (3, (96, 24, 20), (38.4, 9.6, 8.0), 0.2, 0.03, 1.6, 2.0),
+]
+
+
+@pytest.mark.parametrize("case", TILED_PC_CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+@pytest.mark.parametrize("groups", [None, "1", "40"], ids=lambda g: f"groups-{g}")
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gmg_vcycle_parity_tiled(case, groups, precision, monkeypatch):
+    note(f"gmg tiled {case} groups={groups} {precision}")
+    from paper_2006_16764_amd import binding
+    if groups is None:
+        monkeypatch.delenv("PF_GMG_TILE_GROUPS", raising=False)
+    else:
+        monkeypatch.setenv("PF_GMG_TILE_GROUPS", groups)
+    mesh, p, U, Up, pb = setup_case(case, 2)
+    r = inputs.random_vector(mesh.n_nodes, 4)
+    z = pb.new_vector()
+    prec = binding.PF_FP64 if precision == "fp64" else binding.PF_FP32
+    pb.pf_precond_setup(dev(U), binding.PF_PC_GMG, prec)
+    pb.pf_precond_apply(dev(r), z)
+    ref = precond.BlockPreconditioner(mesh, U, p, "gmg").apply(r)
+    assert rel(host(z), ref) < (1e-12 if precision == "fp64" else 2e-5)
+    assert pb.close() == 0
+
+
 def test_gmg_is_symmetric_on_gpu():
     note("gmg symmetry")
     from paper_2006_16764_amd import binding
