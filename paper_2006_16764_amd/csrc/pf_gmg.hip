@@ -69,6 +69,7 @@ struct Level {
   typename V2<T>::type* b;       // right-hand side
   typename V2<T>::type* r;       // residual
   typename V2<T>::type* d;       // Chebyshev direction
+  T* dg;                         // phi-block diagonal per node
   int kz;                        // z-march length of the tiled 3-D stencils (0: untiled)
 };
 
@@ -96,6 +97,24 @@ __device__ __forceinline__ void node_ijk(const LvK& g, long long i, int& ix, int
   const long long r = i / g.nn[0];
   iy = DIM == 2 ? (int)r : (int)(r % g.nn[1]);
   iz = DIM == 2 ? 0 : (int)(r / g.nn[1]);
+}
+
+// Node-wise kernels run on a 2-D grid: blockIdx.y is the node plane (z; 0 in
+// 2-D) and blockIdx.x * kT + threadIdx.x the node within the plane, so that the
+// coordinates come from 32-bit arithmetic.  Returns false past the plane's end.
+__device__ __forceinline__ bool plane_node(const LvK& g, int& ix, int& iy, int& iz, long long& i) {
+  const int pn = g.nn[0] * g.nn[1];
+  const int q = (int)blockIdx.x * kT + (int)threadIdx.x;
+  if (q >= pn) return false;
+  iy = q / g.nn[0];
+  ix = q - iy * g.nn[0];
+  iz = (int)blockIdx.y;
+  i = (long long)iz * pn + q;
+  return true;
+}
+
+inline dim3 plane_grid(const LvK& k) {
+  return dim3((unsigned)(((long long)k.nn[0] * k.nn[1] + kT - 1) / kT), (unsigned)k.nn[2]);
 }
 
 // Stencil of node (ix, iy, iz) for both blocks: w[b][t] for the 3^DIM offsets t
@@ -316,6 +335,18 @@ __global__ void k_coarsen(LvK fg, LvK cg, const T* __restrict__ cf, T* __restric
   cc[E] = acc * (T)(DIM == 3 ? 0.125 : 0.25);
 }
 
+// dg[i] = phi-block diagonal of node i (the sum of the coefficients of its
+// cells times the element-matrix diagonal entry)
+template <int DIM, class T>
+__global__ void __launch_bounds__(kT) k_diag(LvK g, const T* __restrict__ c, T* __restrict__ dg) {
+  int ix, iy, iz;
+  long long i;
+  if (!plane_node(g, ix, iy, iz, i)) return;
+  T d0, d1;
+  diag_only<DIM, T>(g, c, ix, iy, iz, d0, d1);
+  dg[i] = d0;
+}
+
 // Chebyshev step flags.  kWriteD: store the step's direction d (only a next
 // step that reads it needs it).  kReadD: read the previous direction from d
 // (a step whose alpha is 0, the first one, needs none).  kDIsX: the previous
@@ -332,11 +363,11 @@ __global__ void __launch_bounds__(kT)
     k_smooth(LvK g, const T* __restrict__ c, typename V2<T>::type* __restrict__ b,
              const typename V2<T>::type* __restrict__ x_in, typename V2<T>::type* __restrict__ x_out,
              typename V2<T>::type* __restrict__ d, T al0, T al1, T be0, T be1,
-             const double2* __restrict__ r64, double2* __restrict__ z64) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= g.nnodes) return;
+             const double2* __restrict__ r64, double2* __restrict__ z64,
+             const T* __restrict__ dgp) {
   int ix, iy, iz;
-  node_ijk<DIM>(g, i, ix, iy, iz);
+  long long i;
+  if (!plane_node(g, ix, iy, iz, i)) return;
   typename V2<T>::type bb;
   if (IN == 1) {
     const double2 rv = r64[i];
@@ -361,7 +392,12 @@ __global__ void __launch_bounds__(kT)
     dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
     dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
   } else {
-    diag_only<DIM, T>(g, c, ix, iy, iz, dg0, dg1);
+    // zero start: the diagonal only (phi block stored at set-up)
+    dg0 = dgp[i];
+    T n = (T)((ix - 1 >= 0 ? 1 : 0) + (ix < g.n[0] ? 1 : 0)) *
+          (T)((iy - 1 >= 0 ? 1 : 0) + (iy < g.n[1] ? 1 : 0));
+    if (DIM == 3) n *= (T)((iz - 1 >= 0 ? 1 : 0) + (iz < g.n[2] ? 1 : 0));
+    dg1 = (T)g.Ae[1][0] * n;
     dn0 = be0 * bb.x / dg0;
     dn1 = be1 * bb.y / dg1;
   }
@@ -383,10 +419,9 @@ template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
     k_resid(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
             const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ r) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= g.nnodes) return;
   int ix, iy, iz;
-  node_ijk<DIM>(g, i, ix, iy, iz);
+  long long i;
+  if (!plane_node(g, ix, iy, iz, i)) return;
   T y0, y1, d0, d1;
   apply_A<DIM, T>(g, c, x, ix, iy, iz, y0, y1, d0, d1);
   const auto bv = b[i];
@@ -402,10 +437,9 @@ template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
     k_restrict(LvK fg, LvK cg, const typename V2<T>::type* __restrict__ rf,
                typename V2<T>::type* __restrict__ bc) {
-  const long long I = (long long)blockIdx.x * kT + threadIdx.x;
-  if (I >= cg.nnodes) return;
   int cx, cy, cz;
-  node_ijk<DIM>(cg, I, cx, cy, cz);
+  long long I;
+  if (!plane_node(cg, cx, cy, cz, I)) return;
   T a0 = 0, a1 = 0;
 #pragma unroll
   for (int dz = -1; dz <= (DIM == 3 ? 1 : -1); ++dz) {
@@ -434,33 +468,63 @@ __global__ void __launch_bounds__(kT)
   bc[I] = o;
 }
 
-// x_f[i] += sum_I P[i, I] e_c[I]
+// x_f[i] += sum_I P[i, I] e_c[I], by coarse node: the thread of coarse node
+// (cx, cy, cz) updates the fine nodes 2c + o, o in {0, 1}^DIM, that exist.  A
+// fine node with odd coordinates along m axes takes the sum of its 2^m coarse
+// neighbours times 2^-m.  Neighbouring threads touch neighbouring fine pairs,
+// so the fine rows are read and written once, coalesced.
 template <int DIM, class T>
 __global__ void __launch_bounds__(kT)
     k_prolong_add(LvK fg, LvK cg, const typename V2<T>::type* __restrict__ ec,
                   typename V2<T>::type* __restrict__ xf) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= fg.nnodes) return;
-  int fx, fy, fz;
-  node_ijk<DIM>(fg, i, fx, fy, fz);
-  const int xs[2] = {fx >> 1, (fx + 1) >> 1};
-  const int ys[2] = {fy >> 1, (fy + 1) >> 1};
-  const int zs[2] = {DIM == 3 ? fz >> 1 : 0, DIM == 3 ? (fz + 1) >> 1 : 0};
-  const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (DIM == 3 && (fz & 1)) ? 2 : 1;
-  const T w = ((fx & 1) ? (T)0.5 : (T)1) * ((fy & 1) ? (T)0.5 : (T)1) *
-              ((DIM == 3 && (fz & 1)) ? (T)0.5 : (T)1);
-  T a0 = 0, a1 = 0;
-  for (int kz = 0; kz < nzs; ++kz)
-    for (int ky = 0; ky < nys; ++ky)
-      for (int kx = 0; kx < nxs; ++kx) {
-        const auto v = ec[nidx(cg, xs[kx], ys[ky], zs[kz])];
-        a0 += v.x;
-        a1 += v.y;
+  using T2 = typename V2<T>::type;
+  int cx, cy, cz;
+  long long I;
+  if (!plane_node(cg, cx, cy, cz, I)) return;
+  const bool hx = cx + 1 < cg.nn[0], hy = cy + 1 < cg.nn[1];
+  const bool hz = DIM == 3 && cz + 1 < cg.nn[2];
+  const long long sy = cg.nn[0], sz = (long long)cg.nn[0] * cg.nn[1];
+  // coarse corner values e[dz][dy][dx]; absent corners are never used
+  T2 e[2][2][2];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const bool ok = (dx == 0 || hx) && (dy == 0 || hy) && (dz == 0 || hz);
+        e[dz][dy][dx] = ok ? ec[I + dx + dy * sy + dz * sz] : ec[I];
       }
-  auto x = xf[i];
-  x.x += w * a0;
-  x.y += w * a1;
-  xf[i] = x;
+  const long long fsy = fg.nn[0], fsz = (long long)fg.nn[0] * fg.nn[1];
+  const long long f0 = 2LL * cx + fsy * (2LL * cy) + (DIM == 3 ? fsz * (2LL * cz) : 0LL);
+#pragma unroll
+  for (int oz = 0; oz < (DIM == 3 ? 2 : 1); ++oz) {
+    if (oz == 1 && !hz) continue;
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      if (oy == 1 && !hy) continue;
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        if (ox == 1 && !hx) continue;
+        T a0 = 0, a1 = 0;
+#pragma unroll
+        for (int kz = 0; kz <= oz; ++kz)
+#pragma unroll
+          for (int ky = 0; ky <= oy; ++ky)
+#pragma unroll
+            for (int kx = 0; kx <= ox; ++kx) {
+              a0 += e[kz][ky][kx].x;
+              a1 += e[kz][ky][kx].y;
+            }
+        const T w = (ox ? (T)0.5 : (T)1) * (oy ? (T)0.5 : (T)1) * (oz ? (T)0.5 : (T)1);
+        const long long i = f0 + ox + fsy * oy + fsz * oz;
+        T2 x = xf[i];
+        x.x += w * a0;
+        x.y += w * a1;
+        xf[i] = x;
+      }
+    }
+  }
 }
 
 
@@ -959,6 +1023,7 @@ int hier_alloc(pf_problem* pb, Hier<T>& H) {
     typename V2<T>::type** bufs[] = {&M.xa, &M.xb, &M.b, &M.r, &M.d};
     for (auto p : bufs)
       if (hipMalloc(p, nb) != hipSuccess) return PF_ERR_OOM;
+    if (hipMalloc(&M.dg, (size_t)M.k.nnodes * sizeof(T)) != hipSuccess) return PF_ERR_OOM;
     bool even = true;
     int mn = 1 << 30;
     for (int k = 0; k < G.dim; ++k) {
@@ -980,7 +1045,7 @@ template <class T>
 hipError_t hier_free(Hier<T>& H) {
   hipError_t first = hipSuccess;
   for (auto& L : H.lv) {
-    void* bufs[] = {L.c, L.xa, L.xb, L.b, L.r, L.d};
+    void* bufs[] = {L.c, L.xa, L.xb, L.b, L.r, L.d, L.dg};
     for (void* p : bufs) {
       if (!p) continue;
       const hipError_t e = hipFree(p);
@@ -1031,6 +1096,8 @@ int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) 
                          H.lv[l - 1].k, L.k, (const T*)H.lv[l - 1].c, L.c);
     }
     PF_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL((k_diag<DIM, T>), plane_grid(L.k), dim3(kT), 0, s, L.k, (const T*)L.c, L.dg);
+    PF_HIP_CHECK(hipGetLastError());
   }
   // per-step coefficients of the coarsest solve, [step][alpha0, alpha1, beta0, beta1]
   const Level<T>& C = H.lv.back();
@@ -1067,10 +1134,10 @@ int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::t
     PF_HIP_CHECK(hipGetLastError());
     return PF_OK;
   }
-  hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT, FL>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+  hipLaunchKernelGGL((k_smooth<DIM, T, IN, OUT, FL>), plane_grid(L.k), dim3(kT), 0, s, L.k,
                      (const T*)L.c, L.b, x_in, x_out, L.d, (T)al[2 * k], (T)al[2 * k + 1],
                      (T)be[2 * k], (T)be[2 * k + 1], reinterpret_cast<const double2*>(r64),
-                     reinterpret_cast<double2*>(z64));
+                     reinterpret_cast<double2*>(z64), (const T*)L.dg);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }
@@ -1147,17 +1214,17 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
                        (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
                        nullptr, L.kz);
   } else {
-    hipLaunchKernelGGL((k_resid<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k,
+    hipLaunchKernelGGL((k_resid<DIM, T>), plane_grid(L.k), dim3(kT), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,
                        (const typename V2<T>::type*)L.xb, L.r);
   }
   PF_HIP_CHECK(hipGetLastError());
   Level<T>& C = H.lv[l + 1];
-  hipLaunchKernelGGL((k_restrict<DIM, T>), dim3(blocks(C.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
+  hipLaunchKernelGGL((k_restrict<DIM, T>), plane_grid(C.k), dim3(kT), 0, s, L.k, C.k,
                      (const typename V2<T>::type*)L.r, C.b);
   PF_HIP_CHECK(hipGetLastError());
   PF_TRY((vcycle<DIM, T>(pb, H, l + 1, nullptr, nullptr, s)));
-  hipLaunchKernelGGL((k_prolong_add<DIM, T>), dim3(blocks(L.k.nnodes)), dim3(kT), 0, s, L.k, C.k,
+  hipLaunchKernelGGL((k_prolong_add<DIM, T>), plane_grid(C.k), dim3(kT), 0, s, L.k, C.k,
                      (const typename V2<T>::type*)C.xb, L.xb);
   PF_HIP_CHECK(hipGetLastError());
   // post-smoothing from the corrected iterate: xb -> xa -> xb (or z64); only
