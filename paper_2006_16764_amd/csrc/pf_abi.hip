@@ -211,6 +211,19 @@ struct Op {
 };
 
 // Right-preconditioned FGMRES(m) from x = 0 for A x = b, |b - A x| <= rtol |b|.
+//
+// Arnoldi with classical Gram-Schmidt and a delayed second projection: step j
+// applies the preconditioner and the operator to V_j as left by step j-1,
+// projected once and normalised by its Pythagorean norm estimate.  One sweep
+// forms the products of V_j and of the new vector w with the basis; V_j is then
+// finished (second projection, exact norm) and w projected once against the
+// finished V_0..V_j in a second sweep.  The finishing step of V_{j+1} at step
+// j+1 completes column j of the Hessenberg matrix:
+//   A z_j = sum_{k<=j} h_k V_k + eta u,  u = sum_{k<=j} s_k V_k + rho V_{j+1}
+// so H[k][j] = h_k + eta s_k and H[j+1][j] = eta rho.  The convergence test
+// uses the column with s = 0, rho = 1; when it passes (or the cycle ends) the
+// products of u are formed at once and the column completed before the exact
+// residual is taken.  Two sweeps over the basis per iteration instead of three.
 int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol,
            const pf_solver_opts& o, int* its_out, hipStream_t s) {
   const long long n = pb->n_dof;
@@ -218,11 +231,13 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   double* V = pb->V;
   double* Z = pb->Z;
   double* r = pb->tmp_vec[3];
-  double* h1 = pb->red_out;
-  double* h2 = pb->red_out + 64;
-  double* nw = pb->red_out + 128;
   double* ydev = pb->red_out + 300;
+  double* dots_dev = pb->red_out + 512;
+  double* cs_dev = pb->red_out + 640;
+  double* ch_dev = pb->red_out + 704;
+  double* hp = pb->host_pinned;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> hcol(m + 1), sv(m + 1), col(m + 1);
   PF_HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), s));
   double beta;
   PF_TRY(norm2(pb, b, &beta, s));
@@ -237,97 +252,146 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   int total = 0;
   bool converged = false;
   double resid = beta;
+  // Givens rotations 0..j-1 applied to column j of H, then rotation j formed
+  // and applied to g; returns |g[j+1]|
+  auto rotate = [&](int j) {
+    for (int i = 0; i < j; ++i) {
+      const double a = H[i * m + j], c = H[(i + 1) * m + j];
+      H[i * m + j] = cs[i] * a + sn[i] * c;
+      H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = H[j * m + j], c = H[(j + 1) * m + j];
+    const double rr = std::hypot(a, c);
+    cs[j] = rr > 0.0 ? a / rr : 1.0;
+    sn[j] = rr > 0.0 ? c / rr : 0.0;
+    H[j * m + j] = rr;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    return std::fabs(g[j + 1]);
+  };
+  // products of V_{j+1} with V_0..V_{j+1}: its second-projection
+  // coefficients sv[0..j] and its norm after that projection
+  auto finish_products = [&](int j, double* rho_out) -> int {
+    PF_TRY(blas_multidot(pb, V, n, j + 2, V + (long long)(j + 1) * n, n, dots_dev, s));
+    PF_HIP_CHECK(hipMemcpyAsync(hp + 512, dots_dev, (j + 2) * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    PF_HIP_CHECK(hipStreamSynchronize(s));
+    double ssq = 0.0;
+    for (int k = 0; k <= j; ++k) {
+      sv[k] = hp[512 + k];
+      ssq += sv[k] * sv[k];
+    }
+    const double r2 = hp[512 + j + 1] - ssq;
+    *rho_out = r2 > 0.0 ? std::sqrt(r2) : 0.0;
+    return PF_OK;
+  };
   while (true) {
-    // V_0 = r / beta
+    // V_0 = r / |r|, final
     PF_TRY(blas_axpby(1.0 / resid, rhs, 0.0, rhs, V, n, s));
     std::fill(g.begin(), g.end(), 0.0);
+    std::fill(H.begin(), H.end(), 0.0);
     g[0] = resid;
-    int jend = 0;
+    int jend = 0;       // completed columns
+    bool pending = false;  // column jend computed, V_{jend+1} not yet finished
+    double eta = 0.0;      // norm estimate that scaled the pending V_{jend+1}
     for (int j = 0; j < m; ++j) {
       double* vj = V + (long long)j * n;
       double* zj = Z + (long long)j * n;
       double* w = V + (long long)(j + 1) * n;
       PF_TRY(pc_apply(pb, vj, zj, s));
       PF_TRY(op.apply(zj, w, s));
-      // classical Gram-Schmidt; the products with V_0..V_j and w itself (the
-      // last entry, |w|^2) come from one pass since w is stored as V_{j+1}
-      PF_TRY(blas_multidot(pb, V, n, j + 2, w, n, h1, s));
-      PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, h1, (j + 2) * sizeof(double),
+      PF_TRY(blas_dcgs_dots(pb, V, n, j, n, dots_dev, s));
+      PF_HIP_CHECK(hipMemcpyAsync(hp + 512, dots_dev, (2 * j + 3) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
       PF_HIP_CHECK(hipStreamSynchronize(s));
-      double* hp = pb->host_pinned;
+      const double* dt = hp + 512;          // V_k . V_j (k < j), |V_j|^2
+      const double* dw = hp + 512 + j + 1;  // V_k . w (k < j), V_j . w, |w|^2
+      // finish V_j: second projection coefficients dt[0..j-1], norm rho
+      double rho = 1.0;
+      if (j > 0) {
+        double ssq = 0.0;
+        for (int k = 0; k < j; ++k) ssq += dt[k] * dt[k];
+        const double r2 = dt[j] - ssq;
+        rho = r2 > 0.0 ? std::sqrt(r2) : 0.0;
+      }
+      if (pending) {
+        for (int k = 0; k < j; ++k) H[k * m + j - 1] = hcol[k] + eta * dt[k];
+        H[j * m + j - 1] = eta * rho;
+        resid = rotate(j - 1);
+        jend = j;
+        pending = false;
+        if (!std::isfinite(resid)) {
+          set_error("non-finite Arnoldi coefficient in FGMRES");
+          return PF_ERR_NONFINITE;
+        }
+        if (resid <= target || rho == 0.0) {
+          converged = resid <= target;
+          break;
+        }
+      }
+      // products of w with the finished V_0..V_j
+      double dot_wv = dw[j];
+      if (j > 0) {
+        double c = 0.0;
+        for (int k = 0; k < j; ++k) c += dt[k] * dw[k];
+        dot_wv = (dw[j] - c) / rho;
+      }
       double hsq = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        H[i * m + j] = hp[i];
-        hsq += hp[i] * hp[i];
+      for (int k = 0; k < j; ++k) {
+        hcol[k] = dw[k];
+        hsq += dw[k] * dw[k];
       }
-      const double wsq = hp[j + 1];
-      double hn;
-      if (wsq - hsq > 0.5 * wsq) {
-        // less than half the norm removed: one projection is orthogonal to
-        // working accuracy, and |w - V h|^2 = |w|^2 - |h|^2 holds to a few
-        // ulps, so the update and the normalisation are one sweep
-        hn = std::sqrt(wsq - hsq);
-        PF_TRY(blas_axpy_scale(V, n, j + 1, h1, 1.0 / hn, w, n, s));
-      } else if (j + 1 <= kAxpyMultidotMax) {
-        // second projection (CGS2): its products come out of the first update
-        PF_TRY(blas_axpy_multidot(pb, V, n, j + 1, h1, w, n, h2, s));
-        PF_HIP_CHECK(hipMemcpyAsync(hp + 64, h2, (j + 2) * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
-        PF_HIP_CHECK(hipStreamSynchronize(s));
-        double h2sq = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          H[i * m + j] += hp[64 + i];
-          h2sq += hp[64 + i] * hp[64 + i];
-        }
-        const double w2sq = hp[64 + j + 1];
-        if (h2sq <= 0.5 * w2sq) {
-          hn = std::sqrt(w2sq - h2sq);
-          if (hn > 0.0) PF_TRY(blas_axpy_scale(V, n, j + 1, h2, 1.0 / hn, w, n, s));
-        } else {
-          PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
-          PF_TRY(fetch(pb, nw, 1, s));
-          hn = std::sqrt(pb->host_pinned[0]);
-          if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
-        }
-      } else {
-        // second projection for bases beyond the fused kernel's width
-        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h1, w, n, nullptr, 0, s));
-        PF_TRY(blas_multidot(pb, V, n, j + 1, w, n, h2, s));
-        PF_TRY(blas_axpy_dot(pb, V, n, j + 1, h2, w, n, nw, 1, s));
-        PF_HIP_CHECK(hipMemcpyAsync(hp + 64, h2, 65 * sizeof(double), hipMemcpyDeviceToHost, s));
-        PF_HIP_CHECK(hipStreamSynchronize(s));
-        for (int i = 0; i <= j; ++i) H[i * m + j] += hp[64 + i];
-        hn = std::sqrt(hp[128]);
-        if (hn > 0.0) PF_TRY(blas_axpby(1.0 / hn, w, 0.0, w, w, n, s));
-      }
-      H[(j + 1) * m + j] = hn;
-      if (!std::isfinite(hn)) {
+      hcol[j] = dot_wv;
+      hsq += dot_wv * dot_wv;
+      const double wsq = dw[j + 1];
+      if (!std::isfinite(wsq) || !std::isfinite(hsq)) {
         set_error("non-finite Arnoldi coefficient in FGMRES");
         return PF_ERR_NONFINITE;
       }
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], c = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * c;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      for (int k = 0; k < j; ++k) hp[640 + k] = dt[k];
+      for (int k = 0; k <= j; ++k) hp[704 + k] = hcol[k];
+      PF_HIP_CHECK(hipMemcpyAsync(cs_dev, hp + 640, 128 * sizeof(double), hipMemcpyHostToDevice, s));
+      // normalisation of the once-projected w: the Pythagorean estimate while
+      // it keeps at least six digits, else the norm itself
+      const double u2 = wsq - hsq;
+      const bool explicit_norm = !(u2 > 1e-12 * wsq);
+      eta = explicit_norm ? 1.0 : std::sqrt(u2);
+      PF_TRY(blas_dcgs_update(V, n, j, cs_dev, ch_dev, 1.0 / rho, 1.0 / eta, n, s));
+      if (explicit_norm) {
+        PF_TRY(norm2(pb, w, &eta, s));
+        if (eta > 0.0) PF_TRY(blas_axpby(1.0 / eta, w, 0.0, w, w, n, s));
       }
-      const double a = H[j * m + j], c = H[(j + 1) * m + j];
-      const double rr = std::hypot(a, c);
-      cs[j] = rr > 0.0 ? a / rr : 1.0;
-      sn[j] = rr > 0.0 ? c / rr : 0.0;
-      H[j * m + j] = rr;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
       ++total;
-      jend = j + 1;
-      resid = std::fabs(g[j + 1]);
-      if (resid <= target) {
-        converged = true;
-        break;
+      pending = true;
+      // convergence test on the column with the second projection of
+      // V_{j+1} taken as zero
+      for (int k = 0; k <= j; ++k) col[k] = hcol[k];
+      col[j + 1] = eta;
+      for (int i = 0; i < j; ++i) {
+        const double a = col[i], c = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * c;
+        col[i + 1] = -sn[i] * a + cs[i] * c;
       }
-      if (total >= o.gmres_maxit || hn == 0.0) break;
+      const double rr = std::hypot(col[j], col[j + 1]);
+      const double est = rr > 0.0 ? std::fabs(g[j] * col[j + 1] / rr) : std::fabs(g[j]);
+      const bool last = j + 1 == m || total >= o.gmres_maxit || eta == 0.0;
+      if (est <= target || last) {
+        double rho1 = 0.0;
+        if (eta > 0.0) PF_TRY(finish_products(j, &rho1));
+        else std::fill(sv.begin(), sv.begin() + j + 1, 0.0);
+        for (int k = 0; k <= j; ++k) H[k * m + j] = hcol[k] + eta * sv[k];
+        H[(j + 1) * m + j] = eta * rho1;
+        resid = rotate(j);
+        jend = j + 1;
+        pending = false;
+        if (!std::isfinite(resid)) {
+          set_error("non-finite Arnoldi coefficient in FGMRES");
+          return PF_ERR_NONFINITE;
+        }
+        converged = resid <= target;
+        if (converged || last || rho1 == 0.0) break;
+      }
     }
     // y = H^-1 g (upper triangular), x += Z y
     for (int i = jend - 1; i >= 0; --i) {
@@ -694,9 +758,10 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   const int NA = 1 << pb->geo.dim;
   pb->elem_buf_len = pb->geo.dim == 2 ? (long long)4 * NA * pb->geo.n_elems : 1;
   pb->side_len = pb->geo.dim == 3 ? fused3_side_len(pb->geo) : 1;
-  if (hipMalloc(&pb->red_partials, (size_t)64 * pb->n_red_blocks * sizeof(double)) != hipSuccess ||
-      hipMalloc(&pb->red_out, 512 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&pb->host_pinned, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+  if (hipMalloc(&pb->red_partials, (size_t)kRedRows * pb->n_red_blocks * sizeof(double)) !=
+          hipSuccess ||
+      hipMalloc(&pb->red_out, 1024 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&pb->host_pinned, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipMalloc(&pb->elem_buf, (size_t)pb->elem_buf_len * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->side_buf, (size_t)pb->side_len * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->vjp_partials, (size_t)2 * pb->n_elem_blocks * sizeof(double)) != hipSuccess ||

@@ -100,101 +100,96 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// w[i] -= sum_j coef[j] V_j[i]; partials of |w_new|^2 when want_norm
-__global__ void __launch_bounds__(kRedThreads)
-    k_axpy_norm(const double* __restrict__ V, long long ld, int k, const double* __restrict__ coef,
-                double* __restrict__ w, long long n, double* __restrict__ partials, int want_norm) {
-  __shared__ double sh[kRedThreads / 64];
-  const long long n2 = n / 2;
-  double2* w2 = reinterpret_cast<double2*>(w);
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
-       i += (long long)gridDim.x * kRedThreads) {
-    double2 a = w2[i];
-    for (int j = 0; j < k; ++j) {
-      const double c = coef[j];
-      const double2 v = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
-      a.x = fma(-c, v.x, a.x);
-      a.y = fma(-c, v.y, a.y);
-    }
-    w2[i] = a;
-    acc = fma(a.x, a.x, acc);
-    acc = fma(a.y, a.y, acc);
-  }
-  if (want_norm) {
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
-  }
-}
-
-// w <- w - sum_j coef[j] V_j (j < k) and, in the same sweep, the partials of
-// V_j . w_new (rows j < k) and of |w_new|^2 (row k): exactly the products the
-// second Gram-Schmidt projection needs, so that pass does not read V again.
-// KMAX bounds k at compile time so the accumulators stay in registers.
+// Products of one Gram-Schmidt step with a delayed second projection, in one
+// sweep.  t = V_j (the previous direction, projected once) and w = V_{j+1} (the
+// new operator output); rows of partials:
+//   k < j: V_k . t,   j: t . t,   j + 1 + k (k < j): V_k . w,
+//   2j + 1: t . w,    2j + 2: w . w.
+// blockIdx.y takes V_k for k in [KMAX y, KMAX (y + 1)); chunk 0 also forms the
+// three products of t and w.
 template <int KMAX>
 __global__ void __launch_bounds__(kRedThreads)
-    k_axpy_multidot(const double* __restrict__ V, long long ld, int k,
-                    const double* __restrict__ coef, double* __restrict__ w, long long n,
-                    double* __restrict__ partials) {
+    k_dcgs_dots(const double* __restrict__ V, long long ld, int j, long long n,
+                double* __restrict__ partials) {
   __shared__ double sh[kRedThreads / 64];
   const int nb = gridDim.x;
+  const int k0 = blockIdx.y * KMAX;
+  const bool first = blockIdx.y == 0;
   const long long n2 = n / 2;
-  double2* w2 = reinterpret_cast<double2*>(w);
-  double acc[KMAX + 1];
+  const double2* t2 = reinterpret_cast<const double2*>(V + (long long)j * ld);
+  const double2* w2 = reinterpret_cast<const double2*>(V + (long long)(j + 1) * ld);
+  double at[KMAX], aw[KMAX];
 #pragma unroll
-  for (int j = 0; j <= KMAX; ++j) acc[j] = 0.0;
+  for (int q = 0; q < KMAX; ++q) at[q] = aw[q] = 0.0;
+  double tt = 0.0, tw = 0.0, ww = 0.0;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
        i += (long long)nb * kRedThreads) {
-    double2 a = w2[i];
-    double2 v[KMAX];
+    const double2 t = t2[i], w = w2[i];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      if (j < k) {
-        v[j] = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
-        const double c = coef[j];
-        a.x = fma(-c, v[j].x, a.x);
-        a.y = fma(-c, v[j].y, a.y);
+    for (int q = 0; q < KMAX; ++q) {
+      if (k0 + q < j) {
+        const double2 v = reinterpret_cast<const double2*>(V + (long long)(k0 + q) * ld)[i];
+        at[q] = fma(v.x, t.x, at[q]);
+        at[q] = fma(v.y, t.y, at[q]);
+        aw[q] = fma(v.x, w.x, aw[q]);
+        aw[q] = fma(v.y, w.y, aw[q]);
       }
     }
-    w2[i] = a;
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) {
-      if (j < k) {
-        acc[j] = fma(v[j].x, a.x, acc[j]);
-        acc[j] = fma(v[j].y, a.y, acc[j]);
-      }
-    }
-    acc[KMAX] = fma(a.x, a.x, acc[KMAX]);
-    acc[KMAX] = fma(a.y, a.y, acc[KMAX]);
-  }
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j) {
-    if (j < k) {
-      const double t = block_sum(acc[j], sh);
-      if (threadIdx.x == 0) partials[(long long)j * nb + blockIdx.x] = t;
+    if (first) {
+      tt = fma(t.x, t.x, tt);
+      tt = fma(t.y, t.y, tt);
+      tw = fma(t.x, w.x, tw);
+      tw = fma(t.y, w.y, tw);
+      ww = fma(w.x, w.x, ww);
+      ww = fma(w.y, w.y, ww);
     }
   }
-  const double t = block_sum(acc[KMAX], sh);
-  if (threadIdx.x == 0) partials[(long long)k * nb + blockIdx.x] = t;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (k0 + q < j) {
+      const double a = block_sum(at[q], sh);
+      if (threadIdx.x == 0) partials[(long long)(k0 + q) * nb + blockIdx.x] = a;
+      const double b = block_sum(aw[q], sh);
+      if (threadIdx.x == 0) partials[(long long)(j + 1 + k0 + q) * nb + blockIdx.x] = b;
+    }
+  }
+  if (first) {
+    const double a = block_sum(tt, sh);
+    if (threadIdx.x == 0) partials[(long long)j * nb + blockIdx.x] = a;
+    const double b = block_sum(tw, sh);
+    if (threadIdx.x == 0) partials[(long long)(2 * j + 1) * nb + blockIdx.x] = b;
+    const double c = block_sum(ww, sh);
+    if (threadIdx.x == 0) partials[(long long)(2 * j + 2) * nb + blockIdx.x] = c;
+  }
 }
 
-// w <- scale * (w - sum_j coef[j] V_j)
+// The two updates of that step in one sweep, in place:
+//   t <- (t - sum_{k<j} cs[k] V_k) * inv_rho           (the final V_j; j > 0)
+//   w <- (w - sum_{k<j} ch[k] V_k - ch[j] t_new) * inv_eta
 __global__ void __launch_bounds__(256)
-    k_axpy_scale(const double* __restrict__ V, long long ld, int k,
-                 const double* __restrict__ coef, double scale, double* __restrict__ w,
-                 long long n) {
+    k_dcgs_update(double* __restrict__ V, long long ld, int j, const double* __restrict__ cs,
+                  const double* __restrict__ ch, double inv_rho, double inv_eta, long long n) {
   const long long n2 = n / 2;
-  double2* w2 = reinterpret_cast<double2*>(w);
+  double2* t2 = reinterpret_cast<double2*>(V + (long long)j * ld);
+  double2* w2 = reinterpret_cast<double2*>(V + (long long)(j + 1) * ld);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
-    double2 a = w2[i];
-    for (int j = 0; j < k; ++j) {
-      const double c = coef[j];
-      const double2 v = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
-      a.x = fma(-c, v.x, a.x);
-      a.y = fma(-c, v.y, a.y);
+    double2 t = t2[i], w = w2[i];
+    for (int k = 0; k < j; ++k) {
+      const double2 v = reinterpret_cast<const double2*>(V + (long long)k * ld)[i];
+      const double a = cs[k], b = ch[k];
+      t.x = fma(-a, v.x, t.x);
+      t.y = fma(-a, v.y, t.y);
+      w.x = fma(-b, v.x, w.x);
+      w.y = fma(-b, v.y, w.y);
     }
-    w2[i] = make_double2(scale * a.x, scale * a.y);
+    t.x *= inv_rho;
+    t.y *= inv_rho;
+    const double c = ch[j];
+    w.x = fma(-c, t.x, w.x) * inv_eta;
+    w.y = fma(-c, t.y, w.y) * inv_eta;
+    if (j > 0) t2[i] = t;  // V_0 is final as given
+    w2[i] = w;
   }
 }
 
@@ -266,45 +261,31 @@ int blas_dot(pf_problem* pb, const double* x, const double* y, long long n, doub
   return blas_multidot(pb, x, n, 1, y, n, out_dev, s);
 }
 
-int blas_axpy_dot(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
-                  double* w, long long n, double* dots_dev, int want_norm, hipStream_t s) {
+int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long long n,
+                   double* out_dev, hipStream_t s) {
+  if (j < 0 || 2 * j + 3 > kRedRows) return PF_ERR_INVALID_ARG;
   const int nb = pb->n_red_blocks;
-  hipLaunchKernelGGL(k_axpy_norm, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k, coef_dev, w, n,
-                     pb->red_partials, want_norm);
-  PF_HIP_CHECK(hipGetLastError());
-  if (want_norm) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, pb->red_partials, nb, dots_dev,
-                       1.0);
-    PF_HIP_CHECK(hipGetLastError());
+  if (j <= 8) {
+    hipLaunchKernelGGL(k_dcgs_dots<8>, dim3(nb, 1), dim3(kRedThreads), 0, s, V, ld, j, n,
+                       pb->red_partials);
+  } else if (j <= 16) {
+    hipLaunchKernelGGL(k_dcgs_dots<16>, dim3(nb, 1), dim3(kRedThreads), 0, s, V, ld, j, n,
+                       pb->red_partials);
+  } else {
+    hipLaunchKernelGGL(k_dcgs_dots<16>, dim3(nb, (j + 15) / 16), dim3(kRedThreads), 0, s, V, ld,
+                       j, n, pb->red_partials);
   }
-  return PF_OK;
-}
-
-int blas_axpy_multidot(pf_problem* pb, const double* V, long long ld, int k,
-                       const double* coef_dev, double* w, long long n, double* out_dev,
-                       hipStream_t s) {
-  if (k < 1 || k > kAxpyMultidotMax) return PF_ERR_INVALID_ARG;
-  const int nb = pb->n_red_blocks;
-  if (k <= 8)
-    hipLaunchKernelGGL(k_axpy_multidot<8>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k, coef_dev,
-                       w, n, pb->red_partials);
-  else if (k <= 16)
-    hipLaunchKernelGGL(k_axpy_multidot<16>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k,
-                       coef_dev, w, n, pb->red_partials);
-  else
-    hipLaunchKernelGGL(k_axpy_multidot<32>, dim3(nb), dim3(kRedThreads), 0, s, V, ld, k,
-                       coef_dev, w, n, pb->red_partials);
   PF_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(kRedThreads), 0, s, pb->red_partials, nb,
+  hipLaunchKernelGGL(k_reduce, dim3(2 * j + 3), dim3(kRedThreads), 0, s, pb->red_partials, nb,
                      out_dev, 1.0);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }
 
-int blas_axpy_scale(const double* V, long long ld, int k, const double* coef_dev, double scale,
-                    double* w, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_scale, dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, s, V, ld, k,
-                     coef_dev, scale, w, n);
+int blas_dcgs_update(double* V, long long ld, int j, const double* cs_dev, const double* ch_dev,
+                     double inv_rho, double inv_eta, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_update, dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, s, V, ld, j,
+                     cs_dev, ch_dev, inv_rho, inv_eta, n);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

@@ -536,7 +536,13 @@ __global__ void __launch_bounds__(kT)
 // stencil use.  kz is chosen per level: long marches on the finest level, short
 // ones on coarse levels, whose few tiles would otherwise leave most compute
 // units idle while a handful of workgroups step through their planes.
-constexpr int SBX = 32, SBY = 8, SKZ = 32;
+#ifndef PF_SBX
+#define PF_SBX 32
+#endif
+#ifndef PF_SBY
+#define PF_SBY 8
+#endif
+constexpr int SBX = PF_SBX, SBY = PF_SBY, SKZ = 32;
 #ifndef PF_TILED_MIN_GROUPS
 #define PF_TILED_MIN_GROUPS 4096
 #endif

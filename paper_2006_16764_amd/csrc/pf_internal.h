@@ -136,17 +136,15 @@ int blas_dot(pf_problem* pb, const double* x, const double* y, long long n, doub
              hipStream_t s);
 int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const double* w,
                   long long n, double* out_dev, hipStream_t s);
-int blas_axpy_dot(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
-                  double* w, long long n, double* dots_dev, int want_norm, hipStream_t s);
-// w <- w - V coef (k vectors) and out[0..k-1] = V^T w_new, out[k] = |w_new|^2,
-// one sweep; k <= kAxpyMultidotMax
-constexpr int kAxpyMultidotMax = 32;
-int blas_axpy_multidot(pf_problem* pb, const double* V, long long ld, int k,
-                       const double* coef_dev, double* w, long long n, double* out_dev,
-                       hipStream_t s);
-// w <- scale * (w - V coef), one sweep
-int blas_axpy_scale(const double* V, long long ld, int k, const double* coef_dev, double scale,
-                    double* w, long long n, hipStream_t s);
+// Rows of the reduction workspace (red_partials holds kRedRows * n_red_blocks).
+constexpr int kRedRows = 128;
+// One Gram-Schmidt step with a delayed second projection (t = V_j, w = V_{j+1}):
+// out[0..2j+2] = V_{<j}^T t, t.t, V_{<j}^T w, t.w, w.w in one sweep; then the
+// in-place updates t <- (t - V_{<j} cs) inv_rho, w <- (w - V_{<j} ch - ch[j] t) inv_eta.
+int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long long n,
+                   double* out_dev, hipStream_t s);
+int blas_dcgs_update(double* V, long long ld, int j, const double* cs_dev, const double* ch_dev,
+                     double inv_rho, double inv_eta, long long n, hipStream_t s);
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
                  double* x, long long n, hipStream_t s);
 int blas_scale_copy(const double* x, const double* alpha_dev, int invert, double* y,
@@ -189,9 +187,9 @@ struct pf_problem {
 
   // reduction scratch: partial sums [k][n_red_blocks] and results
   int n_red_blocks;
-  double* red_partials;  // 64 * n_red_blocks
-  double* red_out;       // 512 doubles of device results
-  double* host_pinned;   // 512 doubles of pinned host staging
+  double* red_partials;  // kRedRows * n_red_blocks
+  double* red_out;       // 1024 doubles of device results
+  double* host_pinned;   // 1024 doubles of pinned host staging
 
   // residual-family scratch
   double* elem_buf;      // element contributions (element pass)
