@@ -572,15 +572,45 @@ inline long long tiled_min_groups() {
   return kTiledMinGroups;
 }
 
-// OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
-// writing the FP64 interleaved z64 (last step of the V-cycle).
-template <class T, int OP, int FL>
-__global__ void __launch_bounds__(SBX * SBY)
-    k_stencil3(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
-               const typename V2<T>::type* __restrict__ x, typename V2<T>::type* __restrict__ out,
-               typename V2<T>::type* __restrict__ d, T al0, T al1, T be0, T be1,
-               double2* __restrict__ z64, int kz) {
+// Arguments of the tiled kernel.  al, be: the step's Chebyshev coefficients
+// per block.  OP 3/4 also take the first (zero-start) step's betas zb, the
+// stored phi-block diagonal dg and, for OP 3, the FP64 right-hand side r64
+// whose FP32 copy they write to bout.
+template <class T>
+struct StArgs {
   using T2 = typename V2<T>::type;
+  const T* c;
+  const T2* b;
+  const T2* x;
+  T2* out;
+  T2* d;
+  T al0, al1, be0, be1;
+  double2* z64;
+  int kz;
+  T zb0, zb1;
+  const double2* r64;
+  T2* bout;
+  const T* dg;
+};
+
+// OP 0: r = b - A x.  OP 1: Chebyshev step (x_out, d).  OP 2: Chebyshev step
+// writing the FP64 interleaved z64 (last step of the V-cycle).  OP 3/4: the
+// first two steps from x = 0 in one sweep: the zero-start iterate
+// x1 = zb D^-1 b is formed while the halo planes are staged (from the FP64 r64,
+// OP 3, or from b, OP 4) and the second step is taken on it; its direction is
+// x1 itself.
+template <class T, int OP, int FL>
+__global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
+  using T2 = typename V2<T>::type;
+  const T* __restrict__ c = A.c;
+  const T2* __restrict__ b = A.b;
+  const T2* __restrict__ x = A.x;
+  T2* __restrict__ out = A.out;
+  T2* __restrict__ d = A.d;
+  const T al0 = A.al0, al1 = A.al1, be0 = A.be0, be1 = A.be1;
+  double2* __restrict__ z64 = A.z64;
+  const int kz = A.kz;
+  constexpr bool ZS = OP >= 3;  // fused zero start
   __shared__ T2 xs[3][SBY + 2][SBX + 2];
   __shared__ T cs[2][SBY + 1][SBX + 1];
   const int tid = threadIdx.x;
@@ -620,21 +650,62 @@ __global__ void __launch_bounds__(SBX * SBY)
   }
   T2 rx[NX];
   T rc[NC];
+  // zero start: raw right-hand side and diagonal of the fetched halo plane, the
+  // in-plane cell counts of the halo nodes (u-block diagonal) and the plane
+  double2 rr[OP == 3 ? NX : 1];
+  T rdg[ZS ? NX : 1], cxy[ZS ? NX : 1];
+  bool rin[ZS ? NX : 1];
+  int fz = 0;
+  if constexpr (ZS) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const int q = tid + j * SBX * SBY;
+      const int gx = x0 - 1 + q % (SBX + 2), gy = y0 - 1 + q / (SBX + 2);
+      cxy[j] = (T)((gx - 1 >= 0 ? 1 : 0) + (gx < g.n[0] ? 1 : 0)) *
+               (T)((gy - 1 >= 0 ? 1 : 0) + (gy < g.n[1] ? 1 : 0));
+    }
+  }
   auto fetch_x = [&](int z) {
     const bool zin = z >= 0 && z < g.nn[2];
-    const T2* xp = x + plane_n * (zin ? z : 0);
+    const long long po = plane_n * (zin ? z : 0);
+    fz = z;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       rx[j].x = 0;
       rx[j].y = 0;
-      if (zin && okx[j]) rx[j] = xp[offx[j]];
+      if constexpr (ZS) {
+        rin[j] = zin && okx[j];
+        rdg[j] = 1;
+        if constexpr (OP == 3) rr[j] = make_double2(0.0, 0.0);
+        if (rin[j]) {
+          rdg[j] = A.dg[po + offx[j]];
+          if constexpr (OP == 3) rr[j] = A.r64[po + offx[j]];
+          else rx[j] = b[po + offx[j]];
+        }
+      } else {
+        if (zin && okx[j]) rx[j] = x[po + offx[j]];
+      }
     }
   };
   auto store_x = [&](int slot) {
+    T czf = 1;
+    if constexpr (ZS) czf = (T)((fz - 1 >= 0 ? 1 : 0) + (fz < g.n[2] ? 1 : 0));
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const int q = tid + j * SBX * SBY;
-      if (q < NQX) (&xs[slot][0][0])[q] = rx[j];
+      T2 v = rx[j];
+      if constexpr (ZS) {
+        // x1 = zb D^-1 b at the halo node (0 outside the mesh)
+        T2 bv = rx[j];
+        if constexpr (OP == 3) {
+          bv.x = (T)rr[j].x;
+          bv.y = (T)rr[j].y;
+        }
+        const T dg1 = (T)g.Ae[1][0] * (cxy[j] * czf);
+        v.x = rin[j] ? A.zb0 * bv.x / rdg[j] : (T)0;
+        v.y = rin[j] ? A.zb1 * bv.y / dg1 : (T)0;
+      }
+      if (q < NQX) (&xs[slot][0][0])[q] = v;
     }
   };
   auto fetch_c = [&](int zc) {
@@ -780,7 +851,15 @@ __global__ void __launch_bounds__(SBX * SBY)
       }
       const T dg0 = (T)g.Ae[0][0] * Sall, dg1 = (T)g.Ae[1][0] * f[0];
       const long long i = ibase + plane_n * z;
-      const T2 bb = b[i];
+      T2 bb;
+      if constexpr (OP == 3) {
+        const double2 rv = A.r64[i];
+        bb.x = (T)rv.x;
+        bb.y = (T)rv.y;
+        A.bout[i] = bb;
+      } else {
+        bb = b[i];
+      }
       const T r0 = bb.x - y0, r1 = bb.y - y1;
       if (OP == 0) {
         T2 o;
@@ -791,7 +870,7 @@ __global__ void __launch_bounds__(SBX * SBY)
         const T2 xi = xs[s0][ty + 1][tx + 1];
         T2 dv = xi;
         if (FL & kReadD) dv = d[i];
-        if (!(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
+        if (!ZS && !(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
         const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
         const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
         if (OP == 2) {
@@ -1133,10 +1212,19 @@ int smooth_step(Level<T>& L, const typename V2<T>::type* x_in, typename V2<T>::t
                 hipStream_t s) {
   if (IN == 2 && L.kz > 0) {
     constexpr int OP = OUT == 1 ? 2 : 1;
-    hipLaunchKernelGGL((k_stencil3<T, OP, FL>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k,
-                       (const T*)L.c, (const typename V2<T>::type*)L.b, x_in, x_out, L.d,
-                       (T)al[2 * k], (T)al[2 * k + 1], (T)be[2 * k], (T)be[2 * k + 1],
-                       reinterpret_cast<double2*>(z64), L.kz);
+    StArgs<T> A{};
+    A.c = L.c;
+    A.b = L.b;
+    A.x = x_in;
+    A.out = x_out;
+    A.d = L.d;
+    A.al0 = (T)al[2 * k];
+    A.al1 = (T)al[2 * k + 1];
+    A.be0 = (T)be[2 * k];
+    A.be1 = (T)be[2 * k + 1];
+    A.z64 = reinterpret_cast<double2*>(z64);
+    A.kz = L.kz;
+    hipLaunchKernelGGL((k_stencil3<T, OP, FL>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k, A);
     PF_HIP_CHECK(hipGetLastError());
     return PF_OK;
   }
@@ -1210,15 +1298,41 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   double al[4], be[4];
   smoother_coefs(L, al, be);
   // pre-smoothing from zero: xa, then xb.  The first direction equals xa, and
-  // the post-smoothing restarts with alpha = 0: neither step stores d.
-  if (top) PF_TRY((smooth_step<DIM, T, 1, 0, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
-  else PF_TRY((smooth_step<DIM, T, 0, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
-  PF_TRY((smooth_step<DIM, T, 2, 0, kDIsX>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
+  // the post-smoothing restarts with alpha = 0: neither step stores d.  Tiled
+  // levels take both steps in one sweep.
   if (L.kz > 0) {
-    hipLaunchKernelGGL((k_stencil3<T, 0, 0>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k,
-                       (const T*)L.c, (const typename V2<T>::type*)L.b,
-                       (const typename V2<T>::type*)L.xb, L.r, nullptr, (T)0, (T)0, (T)0, (T)0,
-                       nullptr, L.kz);
+    StArgs<T> A{};
+    A.c = L.c;
+    A.b = L.b;
+    A.out = L.xb;
+    A.al0 = (T)al[2];
+    A.al1 = (T)al[3];
+    A.be0 = (T)be[2];
+    A.be1 = (T)be[3];
+    A.kz = L.kz;
+    A.zb0 = (T)be[0];
+    A.zb1 = (T)be[1];
+    A.r64 = reinterpret_cast<const double2*>(r64);
+    A.bout = L.b;
+    A.dg = L.dg;
+    if (top)
+      hipLaunchKernelGGL((k_stencil3<T, 3, 0>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k, A);
+    else
+      hipLaunchKernelGGL((k_stencil3<T, 4, 0>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k, A);
+    PF_HIP_CHECK(hipGetLastError());
+  } else {
+    if (top) PF_TRY((smooth_step<DIM, T, 1, 0, 0>(L, nullptr, L.xa, al, be, 0, r64, nullptr, s)));
+    else PF_TRY((smooth_step<DIM, T, 0, 0, 0>(L, nullptr, L.xa, al, be, 0, nullptr, nullptr, s)));
+    PF_TRY((smooth_step<DIM, T, 2, 0, kDIsX>(L, L.xa, L.xb, al, be, 1, nullptr, nullptr, s)));
+  }
+  if (L.kz > 0) {
+    StArgs<T> A{};
+    A.c = L.c;
+    A.b = L.b;
+    A.x = L.xb;
+    A.out = L.r;
+    A.kz = L.kz;
+    hipLaunchKernelGGL((k_stencil3<T, 0, 0>), tiled_grid(L), dim3(SBX * SBY), 0, s, L.k, A);
   } else {
     hipLaunchKernelGGL((k_resid<DIM, T>), plane_grid(L.k), dim3(kT), 0, s, L.k,
                        (const T*)L.c, (const typename V2<T>::type*)L.b,
