@@ -93,6 +93,58 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     }
   };
 
+  // Plane prefetch (modes at one wave per SIMD, whose single workgroup per
+  // compute unit would otherwise wait out every plane load): the next-but-one
+  // node plane is read right after the element evaluation and stored to its
+  // LDS slot after the next barrier, so its memory latency is spent in the
+  // node-sum phase.  The residual and FD product run two workgroups per
+  // compute unit, which cover each other's loads, and have no registers to
+  // spare for it.
+  constexpr bool kPrefetch = !(MODE == MODE_RES || MODE == MODE_FD);
+  // Node tid of the plane goes through registers; the few nodes beyond the
+  // first kThreads are read when stored.
+  double2 fu, fp, fv;
+  bool fok;
+  auto fetch_plane = [&](int z) {
+    const int lx = tid % PX, ly = tid / PX;
+    fok = lx <= lxmax && ly <= lymax;
+    if (fok) {
+      const long long g = gnode(G, x0 + lx, y0 + ly, z);
+      fu = U[g];
+      fp = Up[g];
+      if (MI::kHasV) fv = V[g];
+    }
+  };
+  auto store_plane = [&](int slot, int z) {
+    if (fok) {
+      double2 u = fu;
+      if (MODE == MODE_FD) {
+        u.x = fma(eps, fv.x, u.x);
+        u.y = fma(eps, fv.y, u.y);
+      } else if (MI::kHasV) {
+        sv[slot][tid] = fv;
+      }
+      su[slot][tid] = u;
+      sp[slot][tid] = fp;
+    }
+    for (int n = tid + kThreads; n < PN; n += kThreads) {
+      const int lx = n % PX, ly = n / PX;
+      if (lx <= lxmax && ly <= lymax) {
+        const long long g = gnode(G, x0 + lx, y0 + ly, z);
+        double2 u = U[g];
+        if (MODE == MODE_FD) {
+          const double2 v = V[g];
+          u.x = fma(eps, v.x, u.x);
+          u.y = fma(eps, v.y, u.y);
+        } else if (MI::kHasV) {
+          sv[slot][n] = V[g];
+        }
+        su[slot][n] = u;
+        sp[slot][n] = Up[g];
+      }
+    }
+  };
+
   const long long tile_base = (long long)tile * (KZ + 1) * PN;
   // Write the sum of node n (local) of plane lz: final value or side-buffer partial.
   auto emit = [&](int n, int lz, const double* acc) {
@@ -140,10 +192,17 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
 
   double ge = 0.0, gl = 0.0;
   load_plane(0, z0);
+  if (kPrefetch) {
+    load_plane(1, z0 + 1);
+    __syncthreads();
+  }
   for (int kz = 0; kz < kzmax; ++kz) {
     const int bot = kz & 1, top = bot ^ 1;
-    load_plane(top, z0 + kz + 1);
-    __syncthreads();
+    const bool more = kPrefetch && kz + 2 <= kzmax;  // plane z0 + kz + 2 exists in this chunk
+    if (!kPrefetch) {
+      load_plane(top, z0 + kz + 1);
+      __syncthreads();
+    }
     double out[NO][8];
     if (has_elem) {
       double u0[8], u1[8], p0[8], p1[8], v0[8], v1[8];
@@ -186,6 +245,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     for (int o = 0; o < NO; ++o)
 #pragma unroll
       for (int a = 0; a < 4; ++a) cb[o][a][tid] = out[o][a];
+    if (more) fetch_plane(z0 + kz + 2);
     __syncthreads();
     {
       double acc[NO];
@@ -200,6 +260,9 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
         emit(nB, kz, acc);
       }
     }
+    // slot bot (plane kz) is no longer read: every lane has passed the
+    // element evaluation; it takes plane kz + 2
+    if (more) store_plane(bot, z0 + kz + 2);
     __syncthreads();
     // top corners -> carried to plane kz + 1
 #pragma unroll
