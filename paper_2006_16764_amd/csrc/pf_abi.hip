@@ -233,8 +233,6 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   double* r = pb->tmp_vec[3];
   double* ydev = pb->red_out + 300;
   double* dots_dev = pb->red_out + 512;
-  double* cs_dev = pb->red_out + 640;
-  double* ch_dev = pb->red_out + 704;
   double* hp = pb->host_pinned;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   std::vector<double> hcol(m + 1), sv(m + 1), col(m + 1);
@@ -349,15 +347,12 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
         set_error("non-finite Arnoldi coefficient in FGMRES");
         return PF_ERR_NONFINITE;
       }
-      for (int k = 0; k < j; ++k) hp[640 + k] = dt[k];
-      for (int k = 0; k <= j; ++k) hp[704 + k] = hcol[k];
-      PF_HIP_CHECK(hipMemcpyAsync(cs_dev, hp + 640, 128 * sizeof(double), hipMemcpyHostToDevice, s));
       // normalisation of the once-projected w: the Pythagorean estimate while
       // it keeps at least six digits, else the norm itself
       const double u2 = wsq - hsq;
       const bool explicit_norm = !(u2 > 1e-12 * wsq);
       eta = explicit_norm ? 1.0 : std::sqrt(u2);
-      PF_TRY(blas_dcgs_update(V, n, j, cs_dev, ch_dev, 1.0 / rho, 1.0 / eta, n, s));
+      PF_TRY(blas_dcgs_update(V, n, j, dots_dev, hcol[j], 1.0 / rho, 1.0 / eta, n, s));
       if (explicit_norm) {
         PF_TRY(norm2(pb, w, &eta, s));
         if (eta > 0.0) PF_TRY(blas_axpby(1.0 / eta, w, 0.0, w, w, n, s));

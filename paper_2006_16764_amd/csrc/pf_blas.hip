@@ -165,10 +165,12 @@ __global__ void __launch_bounds__(kRedThreads)
 
 // The two updates of that step in one sweep, in place:
 //   t <- (t - sum_{k<j} cs[k] V_k) * inv_rho           (the final V_j; j > 0)
-//   w <- (w - sum_{k<j} ch[k] V_k - ch[j] t_new) * inv_eta
+//   w <- (w - sum_{k<j} ch[k] V_k - hj t_new) * inv_eta
+// cs and ch are rows of the products above, still on the device.
 __global__ void __launch_bounds__(256)
     k_dcgs_update(double* __restrict__ V, long long ld, int j, const double* __restrict__ cs,
-                  const double* __restrict__ ch, double inv_rho, double inv_eta, long long n) {
+                  const double* __restrict__ ch, double hj, double inv_rho, double inv_eta,
+                  long long n) {
   const long long n2 = n / 2;
   double2* t2 = reinterpret_cast<double2*>(V + (long long)j * ld);
   double2* w2 = reinterpret_cast<double2*>(V + (long long)(j + 1) * ld);
@@ -185,9 +187,8 @@ __global__ void __launch_bounds__(256)
     }
     t.x *= inv_rho;
     t.y *= inv_rho;
-    const double c = ch[j];
-    w.x = fma(-c, t.x, w.x) * inv_eta;
-    w.y = fma(-c, t.y, w.y) * inv_eta;
+    w.x = fma(-hj, t.x, w.x) * inv_eta;
+    w.y = fma(-hj, t.y, w.y) * inv_eta;
     if (j > 0) t2[i] = t;  // V_0 is final as given
     w2[i] = w;
   }
@@ -282,10 +283,10 @@ int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long lo
   return PF_OK;
 }
 
-int blas_dcgs_update(double* V, long long ld, int j, const double* cs_dev, const double* ch_dev,
+int blas_dcgs_update(double* V, long long ld, int j, const double* dots_dev, double hj,
                      double inv_rho, double inv_eta, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_dcgs_update, dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, s, V, ld, j,
-                     cs_dev, ch_dev, inv_rho, inv_eta, n);
+                     dots_dev, dots_dev + j + 1, hj, inv_rho, inv_eta, n);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

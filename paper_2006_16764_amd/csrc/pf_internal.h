@@ -140,10 +140,11 @@ int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const do
 constexpr int kRedRows = 128;
 // One Gram-Schmidt step with a delayed second projection (t = V_j, w = V_{j+1}):
 // out[0..2j+2] = V_{<j}^T t, t.t, V_{<j}^T w, t.w, w.w in one sweep; then the
-// in-place updates t <- (t - V_{<j} cs) inv_rho, w <- (w - V_{<j} ch - ch[j] t) inv_eta.
+// in-place updates t <- (t - V_{<j} s) inv_rho, w <- (w - V_{<j} h - hj t) inv_eta with
+// s = out[0..j-1] and h = out[j+1..2j] of that product sweep (left on the device).
 int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long long n,
                    double* out_dev, hipStream_t s);
-int blas_dcgs_update(double* V, long long ld, int j, const double* cs_dev, const double* ch_dev,
+int blas_dcgs_update(double* V, long long ld, int j, const double* dots_dev, double hj,
                      double inv_rho, double inv_eta, long long n, hipStream_t s);
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
                  double* x, long long n, hipStream_t s);
