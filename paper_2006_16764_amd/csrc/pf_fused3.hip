@@ -51,6 +51,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   __shared__ double2 su[2][PN];
   __shared__ double2 sp[2][PN];
   __shared__ double2 sv[MI::kHasV && MODE != MODE_FD ? 2 : 1][MI::kHasV && MODE != MODE_FD ? PN : 1];
+  // FD product: F0 of the staged planes, so that the node writes need no load
+  __shared__ double2 sf[MODE == MODE_FD ? 2 : 1][MODE == MODE_FD ? PN : 1];
   __shared__ double cb[NO][4][kThreads];
 
   const int tid = threadIdx.x;
@@ -84,6 +86,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
           const double2 v = V[g];
           u.x = fma(eps, v.x, u.x);
           u.y = fma(eps, v.y, u.y);
+          sf[slot][n] = F0[g];
         } else if (MI::kHasV) {
           sv[slot][n] = V[g];
         }
@@ -101,6 +104,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   // compute unit, which cover each other's loads, and have no registers to
   // spare for it.
   constexpr bool kPrefetch = !(MODE == MODE_RES || MODE == MODE_FD);
+  static_assert(!(kPrefetch && MODE == MODE_FD), "the prefetch path does not stage F0");
   // Node tid of the plane goes through registers; the few nodes beyond the
   // first kThreads are read when stored.
   double2 fu, fp, fv;
@@ -146,7 +150,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   };
 
   const long long tile_base = (long long)tile * (KZ + 1) * PN;
-  // Write the sum of node n (local) of plane lz: final value or side-buffer partial.
+  // Write the sum of node n (local) of plane lz: final value or side-buffer
+  // partial.  Plane lz is staged in slot lz & 1.
   auto emit = [&](int n, int lz, const double* acc) {
     const int lx = n % PX, ly = n / PX;
     if (lx > lxmax || ly > lymax) return;
@@ -159,7 +164,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     }
     const long long g = gnode(G, x0 + lx, y0 + ly, z0 + lz);
     if (MODE == MODE_FD) {
-      const double2 f0 = F0[g];
+      const double2 f0 = sf[lz & 1][n];
       const double ie = eps == 0.0 ? 0.0 : 1.0 / eps;
       out0[g] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
     } else {
