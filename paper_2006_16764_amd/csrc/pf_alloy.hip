@@ -186,13 +186,14 @@ __global__ void __launch_bounds__(kAlloyBlock)
                  const double2* __restrict__ V, const double* __restrict__ eps_dev,
                  const double* __restrict__ hist, double* __restrict__ E, double* __restrict__ coef) {
   constexpr int NA = 1 << DIM;
-  const long long e = (long long)blockIdx.x * kAlloyBlock + threadIdx.x;
-  if (e >= G.n_elems) return;
-  const long long n0 = G.n[0], n1 = G.n[1];
-  const long long ex = e % n0;
-  const long long rest = e / n0;
-  const long long ey = (DIM == 2) ? rest : rest % n1;
-  const long long ez = (DIM == 2) ? 0 : rest / n1;
+  // blockIdx.y is the element layer (0 in 2-D): coordinates from 32-bit arithmetic
+  const int pe = G.n[0] * G.n[1];
+  const int q = (int)blockIdx.x * kAlloyBlock + (int)threadIdx.x;
+  if (q >= pe) return;
+  const int ey = q / G.n[0];
+  const int ex = q - ey * G.n[0];
+  const int ez = (int)blockIdx.y;
+  const long long e = (long long)ez * pe + q;
   const long long s1 = G.nn[0], s2 = (long long)G.nn[0] * G.nn[1];
   const long long base = ex + s1 * (ey + (long long)G.nn[1] * ez);
   const double eps = (MODE == MODE_FD) ? *eps_dev : 0.0;
@@ -239,7 +240,8 @@ template <int DIM>
 int launch_elem(pf_problem* pb, const AlloyConst& C, int mode, const double* U, const double* Uprev,
                 const double* v, const double* eps_dev, double* coef, hipStream_t s) {
   const Geo& G = pb->geo;
-  const unsigned eb = (unsigned)((G.n_elems + kAlloyBlock - 1) / kAlloyBlock);
+  const dim3 eb((unsigned)(((long long)G.n[0] * G.n[1] + kAlloyBlock - 1) / kAlloyBlock),
+                (unsigned)G.n[2]);
   auto U2 = reinterpret_cast<const double2*>(U);
   auto P2 = reinterpret_cast<const double2*>(Uprev);
   auto V2 = reinterpret_cast<const double2*>(v);

@@ -327,12 +327,14 @@ __global__ void __launch_bounds__(256)
              const double* __restrict__ eps_dev, double2* __restrict__ out0,
              double2* __restrict__ out1) {
   constexpr int NO = ModeInfo<MODE>::NO;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= G.n_nodes) return;
-  const int x = (int)(i % G.nn[0]);
-  const long long r = i / G.nn[0];
-  const int y = (int)(r % G.nn[1]);
-  const int z = (int)(r / G.nn[1]);
+  // blockIdx.y is the node plane: coordinates from 32-bit arithmetic
+  const int pn = G.nn[0] * G.nn[1];
+  const int q = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (q >= pn) return;
+  const int y = q / G.nn[0];
+  const int x = q - y * G.nn[0];
+  const int z = (int)blockIdx.y;
+  const long long i = (long long)z * pn + q;
   const bool ringx = (x % TX == 0) || x == G.n[0];
   const bool ringy = (y % TY == 0) || y == G.n[1];
   const bool ringz = (z % KZ == 0) || z == G.n[2];
@@ -384,8 +386,8 @@ int launch_mode(pf_problem* pb, const double* U, const double* Uprev, const doub
                      d2(v), eps_dev, d2(F0), reinterpret_cast<double2*>(out0),
                      reinterpret_cast<double2*>(out1), pb->side_buf, vjp_part, coef);
   PF_HIP_CHECK(hipGetLastError());
-  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
-  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb), dim3(256), 0, s, G, T, pb->side_buf, d2(F0),
+  const unsigned nb = (unsigned)(((long long)G.nn[0] * G.nn[1] + 255) / 256);
+  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb, G.nn[2]), dim3(256), 0, s, G, T, pb->side_buf, d2(F0),
                      eps_dev, reinterpret_cast<double2*>(out0), reinterpret_cast<double2*>(out1));
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;

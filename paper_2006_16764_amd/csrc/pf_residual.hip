@@ -102,13 +102,14 @@ __global__ void __launch_bounds__(256)
              double2* __restrict__ out1, const double2* __restrict__ F0,
              const double* __restrict__ eps_dev, int fd) {
   constexpr int NA = 1 << DIM;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G.n_nodes) return;
-  const long long nn0 = G.nn[0], nn1 = G.nn[1];
-  const int ix = (int)(i % nn0);
-  const long long r = i / nn0;
-  const int iy = (DIM == 2) ? (int)r : (int)(r % nn1);
-  const int iz = (DIM == 2) ? 0 : (int)(r / nn1);
+  // blockIdx.y is the node plane (0 in 2-D): coordinates from 32-bit arithmetic
+  const int pn = G.nn[0] * G.nn[1];
+  const int q = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+  if (q >= pn) return;
+  const int iy = q / G.nn[0];
+  const int ix = q - iy * G.nn[0];
+  const int iz = (int)blockIdx.y;
+  const long long i = (long long)iz * pn + q;
   double acc[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = 0.0;
@@ -156,7 +157,7 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
                double* vjp_part, double* coef, hipStream_t s) {
   const Geo& G = pb->geo;
   const unsigned eb = (unsigned)((G.n_elems + kElemBlock - 1) / kElemBlock);
-  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
+  const dim3 nb((unsigned)(((long long)G.nn[0] * G.nn[1] + 255) / 256), (unsigned)G.nn[2]);
   auto U2 = reinterpret_cast<const double2*>(U);
   auto P2 = reinterpret_cast<const double2*>(Uprev);
   auto V2 = reinterpret_cast<const double2*>(v);
@@ -201,7 +202,7 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
 int launch_gather2(pf_problem* pb, double* out0, const double* F0, const double* eps_dev, int fd,
                    hipStream_t s) {
   const Geo& G = pb->geo;
-  const unsigned nb = (unsigned)((G.n_nodes + 255) / 256);
+  const dim3 nb((unsigned)(((long long)G.nn[0] * G.nn[1] + 255) / 256), (unsigned)G.nn[2]);
   if (G.dim == 3)
     hipLaunchKernelGGL((k_gather<3, 2>), dim3(nb), dim3(256), 0, s, G, pb->elem_buf,
                        reinterpret_cast<double2*>(out0), nullptr,
