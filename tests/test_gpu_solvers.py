@@ -73,6 +73,31 @@ def test_linear_solve_matches_direct(transpose, pc):
     assert st["gmres_its_total"] < 400
 
 
+@pytest.mark.parametrize("transpose", [0, 1])
+@pytest.mark.parametrize("m", [1, 2, 5])
+def test_linear_solve_with_short_restarts(m, transpose):
+    """Restarted FGMRES(m): every cycle ends on a completed Hessenberg column
+    (the delayed second projection is finished before the cycle's least-squares
+    solve), so short cycles still reach the direct solution."""
+    note(f"linear solve restarts m={m} T={transpose}")
+    from paper_2006_16764_amd import binding
+    w, mesh, p, U0, pb = seed_problem("seed2d_64", 32, dt=0.5)
+    rng = np.random.default_rng(2)
+    U = U0 + 0.05 * rng.standard_normal(U0.shape)
+    b = inputs.random_vector(mesh.n_nodes, 5)
+    pb.pf_precond_setup(dev(U), binding.PF_PC_GMG, 0)
+    x = pb.new_vector()
+    opts = binding.default_opts(jv_mode=binding.PF_JV_ANALYTIC, gmres_m=m, gmres_maxit=3000)
+    st = pb.pf_linear_solve(dev(U), dev(U0), dev(b), x, transpose, 1e-11, opts)
+    J = deriv.jacobian(mesh, U, U0, p)
+    A = J.T if transpose else J
+    ref = spla.spsolve(A.tocsc(), b.reshape(-1)).reshape(-1, 2)
+    assert rel(host(x), ref) < 1e-8, st
+    # the reported residual is the true one
+    r = b.reshape(-1) - A @ host(x).reshape(-1)
+    assert np.linalg.norm(r) <= 2e-11 * np.linalg.norm(b), st
+
+
 @pytest.mark.parametrize("jv", ["fd", "analytic"])
 @pytest.mark.parametrize("pc", ["jacobi", "gmg64", "gmg32"])
 def test_newton_step_matches_oracle(jv, pc):
