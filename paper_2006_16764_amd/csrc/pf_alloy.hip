@@ -72,6 +72,7 @@ __device__ __forceinline__ void alloy_point(const Geo& G, const AlloyConst& C, c
 template <int DIM>
 struct PhysAlloyRes {
   static constexpr int kGxUnroll = 1;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   const AlloyConst& C;
   double ca, car, a2;
@@ -96,6 +97,7 @@ struct PhysAlloyRes {
 template <int DIM>
 struct PhysAlloyJvp {
   static constexpr int kGxUnroll = 1;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   const AlloyConst& C;
   __device__ PhysAlloyJvp(const Geo& g, const AlloyConst& c) : G(g), C(c) {}

@@ -25,8 +25,9 @@
 #include "pf_internal.h"
 
 // Unroll factor of the y-row loop of the 3-D Gauss rule (the z-plane loop is
-// not unrolled; the x-point loop is unrolled or not per physics functor,
-// kGxUnroll): a register-pressure / ILP trade-off.
+// not unrolled; the x-point and y-row loops are unrolled or not per physics
+// functor, kGxUnroll and kGyUnroll, the latter taking this factor when not 1):
+// a register-pressure / ILP trade-off.
 #ifndef PF_GY_UNROLL
 #define PF_GY_UNROLL 3
 #endif
@@ -148,8 +149,7 @@ __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
 #pragma unroll
       for (int o = 0; o < NP; ++o) P[o][a] = 0.0;
     }
-PF_UNROLL(PF_GY_UNROLL)
-    for (int gy = 0; gy < 3; ++gy) {
+    auto row_of_points = [&](int gy) {
       const double by0 = Q1::b0(gy), by1 = Q1::b1(gy);
       const double wrow = Q1::w(gy) * Q1::w(gz) * G.jac;
       const double wb0 = wrow * by0, wb1 = wrow * by1, wih = wrow * ihy;
@@ -246,6 +246,13 @@ PF_UNROLL(PF_GY_UNROLL)
         P[o][2] += wb1 * rp[o][0];
         P[o][3] += wb1 * rp[o][1];
       }
+    };
+    if constexpr (Phys::kGyUnroll == 1) {
+#pragma unroll 1
+      for (int gy = 0; gy < 3; ++gy) row_of_points(gy);
+    } else {
+PF_UNROLL(PF_GY_UNROLL)
+      for (int gy = 0; gy < 3; ++gy) row_of_points(gy);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -425,7 +432,10 @@ struct Aniso {
 // output s = a^2 (phi - phi^n)/dt - (phi - phi^3 - lambda (1 - phi^2)^2 u), f = J.
 template <int DIM>
 struct PhysResidual {
-  static constexpr int kGxUnroll = 1;
+  // all three points of a row unrolled, rows one at a time: more independent
+  // work per row within the two-waves-per-SIMD register budget
+  static constexpr int kGxUnroll = 3;
+  static constexpr int kGyUnroll = 1;
   const Geo& G;
   double ca;   // sum of w_q a^2 over the element (preconditioner coefficient)
   double car;  // the current row's sum of w_x a^2
@@ -457,6 +467,7 @@ struct PhysResidual {
 template <int DIM>
 struct PhysJvp {
   static constexpr int kGxUnroll = 3;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   __device__ PhysJvp(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}
@@ -487,6 +498,7 @@ struct PhysJvp {
 template <int DIM>
 struct PhysVjp {
   static constexpr int kGxUnroll = 3;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   double ge, gl;    // element accumulators
   double ger, glr;  // the current row's sums with the x weights
@@ -542,6 +554,7 @@ struct PhysVjp {
 template <int DIM>
 struct PhysVjpU {
   static constexpr int kGxUnroll = 3;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   __device__ PhysVjpU(const Geo& g) : G(g) {}
   __device__ __forceinline__ void weight(double) {}

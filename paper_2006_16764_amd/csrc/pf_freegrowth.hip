@@ -63,6 +63,7 @@ __device__ __forceinline__ void fg_point(const Geo& G, const FgConst& C, const T
 template <int DIM>
 struct PhysFgRes {
   static constexpr int kGxUnroll = 1;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   const FgConst& C;
   double ca, car, a2;
@@ -86,6 +87,7 @@ struct PhysFgRes {
 template <int DIM>
 struct PhysFgJvp {
   static constexpr int kGxUnroll = 1;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   const FgConst& C;
   __device__ PhysFgJvp(const Geo& g, const FgConst& c) : G(g), C(c) {}
