@@ -347,6 +347,11 @@ __global__ void __launch_bounds__(kT) k_diag(LvK g, const T* __restrict__ c, T* 
   dg[i] = d0;
 }
 
+// num / d for a Jacobi diagonal d: times the hardware reciprocal estimate
+// (1 ulp) in FP32, the IEEE quotient in FP64.
+__device__ __forceinline__ float div_diag(float num, float d) { return num * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double div_diag(double num, double d) { return num / d; }
+
 // Chebyshev step flags.  kWriteD: store the step's direction d (only a next
 // step that reads it needs it).  kReadD: read the previous direction from d
 // (a step whose alpha is 0, the first one, needs none).  kDIsX: the previous
@@ -389,8 +394,8 @@ __global__ void __launch_bounds__(kT)
     typename V2<T>::type dv = xv;
     if (FL & kReadD) dv = d[i];
     if (!(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
-    dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
-    dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
+    dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + div_diag(be0 * r0, dg0);
+    dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + div_diag(be1 * r1, dg1);
   } else {
     // zero start: the diagonal only (phi block stored at set-up)
     dg0 = dgp[i];
@@ -398,8 +403,8 @@ __global__ void __launch_bounds__(kT)
           (T)((iy - 1 >= 0 ? 1 : 0) + (iy < g.n[1] ? 1 : 0));
     if (DIM == 3) n *= (T)((iz - 1 >= 0 ? 1 : 0) + (iz < g.n[2] ? 1 : 0));
     dg1 = (T)g.Ae[1][0] * n;
-    dn0 = be0 * bb.x / dg0;
-    dn1 = be1 * bb.y / dg1;
+    dn0 = div_diag(be0 * bb.x, dg0);
+    dn1 = div_diag(be1 * bb.y, dg1);
   }
   typename V2<T>::type dn;
   dn.x = dn0;
@@ -702,8 +707,8 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
           bv.y = (T)rr[j].y;
         }
         const T dg1 = (T)g.Ae[1][0] * (cxy[j] * czf);
-        v.x = rin[j] ? A.zb0 * bv.x / rdg[j] : (T)0;
-        v.y = rin[j] ? A.zb1 * bv.y / dg1 : (T)0;
+        v.x = rin[j] ? div_diag(A.zb0 * bv.x, rdg[j]) : (T)0;
+        v.y = rin[j] ? div_diag(A.zb1 * bv.y, dg1) : (T)0;
       }
       if (q < NQX) (&xs[slot][0][0])[q] = v;
     }
@@ -871,8 +876,8 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
         T2 dv = xi;
         if (FL & kReadD) dv = d[i];
         if (!ZS && !(FL & (kReadD | kDIsX))) dv.x = dv.y = 0;
-        const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + be0 * r0 / dg0;
-        const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + be1 * r1 / dg1;
+        const T dn0 = (al0 == (T)0 ? (T)0 : al0 * dv.x) + div_diag(be0 * r0, dg0);
+        const T dn1 = (al1 == (T)0 ? (T)0 : al1 * dv.y) + div_diag(be1 * r1, dg1);
         if (OP == 2) {
           z64[i] = make_double2((double)(xi.x + dn0), (double)(xi.y + dn1));
         } else {
@@ -912,8 +917,8 @@ __global__ void __launch_bounds__(1024)
       if (k == 0) {
         T dg0, dg1;
         diag_only<DIM, T>(g, c, ix, iy, iz, dg0, dg1);
-        dn0 = be0 * bb.x / dg0;
-        dn1 = be1 * bb.y / dg1;
+        dn0 = div_diag(be0 * bb.x, dg0);
+        dn1 = div_diag(be1 * bb.y, dg1);
       } else {
         T w0[DIM == 3 ? 27 : 9], w1[DIM == 3 ? 27 : 9];
         stencil<DIM, T>(g, c, ix, iy, iz, w0, w1);
