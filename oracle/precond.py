@@ -31,9 +31,10 @@ COARSE_DEGREE on [lmin, 1.1 lmax].  The V-cycle takes its steps in this order:
   post-smooth from the corrected iterate.
 
 Pins: V-cycle contraction and symmetry tests; repeated V-cycles converge to the
-direct solve.  The detailed smoother constants are this build's reading
-(the paper does not define a geometric multigrid), so the exact V-cycle output
-is "parity unpinned" beyond those properties.
+direct solve.  The detailed smoother constants are a reading of the paper's
+method, not its text (the paper uses algebraic multigrid and defines no
+geometric one), so the exact V-cycle output is "parity unpinned" beyond those
+properties.
 """
 from __future__ import annotations
 
