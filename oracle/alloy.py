@@ -236,3 +236,51 @@ def evolve(mesh: Mesh, U0, t0, p: AlloyParams, steps: int, tau_r: float = 1e-10,
         U, _ = step(mesh, states[max(k - 1, 0)], states[k], t0 + k * p.dt, p, tau_r, tau_a=tau_a)
         states.append(U)
     return states
+
+
+def _local(mesh: Mesh, U, Un, Unm1, t, p: AlloyParams, nodes):
+    """Element rows of the elements around the listed nodes (see oracle.local)."""
+    from .local import elements_around
+    el = Element(mesh)
+    elems = elements_around(mesh, nodes)
+    conn = mesh.connectivity(elems)
+    phin, un = split(Un)
+    hist = history_rate(Un, Unm1, p)
+    # x coordinate of the nodes, as mesh.coords() forms it (numpy linspace)
+    ix = conn % mesh.nn[0]
+    L = mesh.L[0]
+    x = ix * ((L - (-L)) / (mesh.nn[0] - 1)) + (-L)
+    x = np.where(ix == mesh.nn[0] - 1, L, x)
+    return el, conn, phin[conn], un[conn], hist[conn], x
+
+
+def _sum_into(nodes, conn, F1, F2):
+    nodes = np.asarray(nodes, dtype=np.int64)
+    res = np.zeros((nodes.shape[0], 2), dtype=F1.dtype)
+    pos = {int(n): i for i, n in enumerate(nodes)}
+    for e in range(conn.shape[0]):
+        for a in range(conn.shape[1]):
+            i = pos.get(int(conn[e, a]))
+            if i is not None:
+                res[i, 0] += F1[e, a]
+                res[i, 1] += F2[e, a]
+    return res
+
+
+def residual_at(mesh: Mesh, U, Un, Unm1, t, p: AlloyParams, nodes) -> np.ndarray:
+    """Rows of residual() at the listed nodes only, [len(nodes), 2]: row i involves
+    only the elements containing node i."""
+    el, conn, pn, un, hs, x = _local(mesh, U, Un, Unm1, t, p, nodes)
+    phi, u = split(U)
+    F1, F2 = element_residual(el, phi[conn], u[conn], pn, un, hs, x, t, p)
+    return _sum_into(nodes, conn, F1, F2)
+
+
+def jvp_at(mesh: Mesh, U, Un, Unm1, t, v, p: AlloyParams, nodes) -> np.ndarray:
+    """Rows of jvp() at the listed nodes only (complex step on the local elements)."""
+    el, conn, pn, un, hs, x = _local(mesh, U, Un, Unm1, t, p, nodes)
+    phi, u = split(U)
+    vp, vu = split(v)
+    F1, F2 = element_residual(el, phi[conn] + 1j * H_CS * vp[conn], u[conn] + 1j * H_CS * vu[conn],
+                              pn, un, hs, x, t, p)
+    return _sum_into(nodes, conn, F1.imag / H_CS, F2.imag / H_CS)

@@ -3,7 +3,8 @@
 256^3: the residual, FD Jv, analytic Jv and VJP are compared with the oracle at
 sampled nodes (random nodes, nodes on tile and chunk boundaries of the 3-D
 kernels, domain faces, edges and corners, interface nodes), each evaluated by the
-oracle from the elements around it.  1024^2: full residual comparison.  128^3:
+oracle from the elements around it; the alloy residual and its tangents on the
+1024 x 256 x 256 directional-solidification mesh the same way.  1024^2: full residual comparison.  128^3:
 a mixed-precision Newton step equals the FP64-preconditioned one and is
 certified by the oracle's residual.  512^2: the autograd gradient through 20
 checkpointed steps matches central differences on the GPU, and a reduced copy of
@@ -216,3 +217,50 @@ def test_adjoint_reduced_matches_oracle():
     assert abs(L - Lr) < 1e-8 * abs(Lr)
     assert abs(ge - ger) < 1e-6 * abs(ger), (ge, ger)
     assert abs(gl - glr) < 1e-6 * abs(glr) + 1e-12, (gl, glr)
+
+
+def test_fullsize_alloy_3d_at_sampled_nodes():
+    """The alloy model at its benchmark size (1024 x 256 x 256 elements, 135 M
+    unknowns) with a nonzero history rate: residual, analytic Jv and FD Jv at
+    sampled nodes (random, the x faces where G4 is extreme, the front)."""
+    from oracle import alloy
+    from paper_2006_16764_amd import binding
+    w = inputs.alloy_workload("alloy3d_1024x256x256")
+    note("building the 1024x256x256 alloy states")
+    Unm1 = inputs.alloy_initial_state(w)
+    rng = np.random.default_rng(11)
+    Un = Unm1 + 0.01 * rng.standard_normal(Unm1.shape)
+    U = Un + 0.01 * rng.standard_normal(Unm1.shape)
+    v = rng.standard_normal(Unm1.shape)
+    D, l_T, v_pull = w.scales()
+    P = alloy.AlloyParams(dt=w.dt, eps4=w.eps4, lam=w.lam, D=D, k=w.k, l_T=l_T, x_iso=w.x_iso,
+                          v_pull=v_pull, theta=w.theta, delta2=w.delta2)
+    mesh = Mesh(3, list(w.n), list(w.half_width))
+    t = 0.5
+    pb = binding.alloy_problem_for(w, gmres_m_max=1)
+    F, Jv, Jfd = (pb.new_vector() for _ in range(3))
+    Ud, Und, Unm1d, vd = dev(U), dev(Un), dev(Unm1), dev(v)
+    note("alloy 1024x256x256 residual, analytic and FD Jv")
+    pb.pf_alloy_residual(Ud, Und, Unm1d, t, F)
+    pb.pf_alloy_jvp(Ud, Und, Unm1d, t, vd, Jv, mode=binding.PF_JV_ANALYTIC)
+    pb.pf_alloy_jvp(Ud, Und, Unm1d, t, vd, Jfd, mode=binding.PF_JV_FD, F0=F)
+    nn = [k + 1 for k in w.n]
+    pts = [rng.integers(0, nn, size=(300, 3))]
+    faces = rng.integers(0, nn, size=(80, 3))
+    faces[:40, 0] = rng.choice([0, 1], size=40)
+    faces[40:, 0] = rng.choice([nn[0] - 2, nn[0] - 1], size=40)
+    pts.append(faces)
+    ids = [p[:, 0] + nn[0] * (p[:, 1] + nn[1] * p[:, 2]) for p in pts]
+    front = np.nonzero(np.abs(U[:, 0]) < 0.5)[0]
+    ids.append(rng.choice(front, size=min(150, front.size), replace=False))
+    nodes = np.unique(np.concatenate(ids).astype(np.int64))
+    idx = torch.from_numpy(nodes).cuda()
+    pick = lambda t_: t_.view(-1, 2)[idx].cpu().numpy()
+    Fh, Jvh, Jfdh = pick(F), pick(Jv), pick(Jfd)
+    assert pb.close() == 0
+    note(f"alloy oracle rows at {nodes.size} nodes")
+    rF = alloy.residual_at(mesh, U, Un, Unm1, t, P, nodes)
+    assert rel(Fh, rF) < 1e-12
+    rJ = alloy.jvp_at(mesh, U, Un, Unm1, t, v, P, nodes)
+    assert rel(Jvh, rJ) < 1e-12
+    assert rel(Jfdh, rJ) < 1e-5

@@ -186,3 +186,20 @@ def test_complex_step_jacobian_vs_central_differences():
     v = inputs.random_vector(m.n_nodes, 3)
     np.testing.assert_allclose(alloy.jvp(m, U, Un, Unm1, 0.4, v, P).reshape(-1), J @ v.reshape(-1),
                                rtol=0, atol=1e-13 * np.abs(J).max() * np.abs(v).max() * 8)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_local_rows_equal_full_residual_and_tangent(dim):
+    """residual_at / jvp_at (the elements around the listed nodes only, with the
+    nodes' own x coordinates for G4) reproduce the rows of the full assembly."""
+    n, L = ((12, 7), (4.8, 2.8)) if dim == 2 else ((6, 5, 4), (2.4, 2.0, 1.6))
+    m = Mesh(dim, n, L)
+    P = AlloyParams(dt=0.05, eps4=0.03, lam=4.0, D=3.0, k=0.2, l_T=6.0, x_iso=0.7, v_pull=1.3,
+                    theta=0.5)
+    U, Un, Unm1 = (inputs.random_state(dim, n, s) for s in (1, 2, 3))
+    v = inputs.random_vector(m.n_nodes, 4)
+    nodes = np.array([0, 3, 7, m.n[0], m.n_nodes // 2, m.n_nodes - 1])
+    F = alloy.residual(m, U, Un, Unm1, 0.3, P)
+    J = alloy.jvp(m, U, Un, Unm1, 0.3, v, P)
+    assert np.abs(alloy.residual_at(m, U, Un, Unm1, 0.3, P, nodes) - F[nodes]).max() < 1e-13 * np.abs(F).max()
+    assert np.abs(alloy.jvp_at(m, U, Un, Unm1, 0.3, v, P, nodes) - J[nodes]).max() < 1e-13 * np.abs(J).max()
