@@ -93,8 +93,9 @@ class MeshP:
         rev = tuple(range(self.dim))[::-1]
         return np.stack([c.transpose(rev).reshape(-1) for c in g], axis=1)
 
-    def connectivity(self) -> np.ndarray:
-        e = np.arange(self.n_elems)
+    def connectivity(self, elems=None) -> np.ndarray:
+        """[E, (p+1)^dim] node indices of the listed elements (all by default)."""
+        e = np.arange(self.n_elems) if elems is None else np.asarray(elems, dtype=np.int64)
         ijk = [e % self.n[0]]
         rest = e // self.n[0]
         if self.dim == 3:
@@ -282,3 +283,67 @@ def evolve(mesh: MeshP, U0, p: FGParams, steps: int, tau_r: float = 1e-10,
         U, _ = step(mesh, states[max(k - 1, 0)], states[k], p, tau_r, tau_a)
         states.append(U)
     return states
+
+
+def elements_around(mesh: MeshP, nodes) -> np.ndarray:
+    """Elements containing at least one of the listed nodes: along each axis a
+    node at an element boundary (index a multiple of p) lies in the two elements
+    it separates, any other node in one."""
+    nodes = np.asarray(nodes, dtype=np.int64)
+    rem = nodes
+    cand = []
+    for k in range(mesh.dim):
+        i = rem % mesh.nn[k]
+        rem = rem // mesh.nn[k]
+        lo = np.where(i % mesh.p == 0, i // mesh.p - 1, i // mesh.p)
+        hi = i // mesh.p
+        cand.append((lo, hi))
+    out = set()
+    for pick in itertools.product((0, 1), repeat=mesh.dim):
+        e = np.zeros(nodes.shape, dtype=np.int64)
+        ok = np.ones(nodes.shape, dtype=bool)
+        stride = 1
+        for k in range(mesh.dim):
+            ek = cand[k][pick[k]]
+            ok &= (ek >= 0) & (ek < mesh.n[k])
+            e = e + ek * stride
+            stride *= mesh.n[k]
+        out.update(e[ok].tolist())
+    return np.array(sorted(out), dtype=np.int64)
+
+
+def _rows_at(mesh: MeshP, U, Un, Unm1, p: FGParams, nodes, v=None):
+    el = ElementP(mesh)
+    conn = mesh.connectivity(elements_around(mesh, nodes))
+    phi, T = _split(U)
+    phin, Tn = _split(Un)
+    hist = history_rate(Un, Unm1, p)
+    if v is not None:
+        vp, vT = _split(v)
+        phi = phi[conn] + 1j * H_CS * vp[conn]
+        T = T[conn] + 1j * H_CS * vT[conn]
+    else:
+        phi, T = phi[conn], T[conn]
+    F1, F3 = element_residual(el, phi, T, phin[conn], Tn[conn], hist[conn], p)
+    if v is not None:
+        F1, F3 = F1.imag / H_CS, F3.imag / H_CS
+    nodes = np.asarray(nodes, dtype=np.int64)
+    res = np.zeros((nodes.shape[0], 2), dtype=F1.dtype)
+    pos = {int(n): i for i, n in enumerate(nodes)}
+    for e in range(conn.shape[0]):
+        for a in range(conn.shape[1]):
+            i = pos.get(int(conn[e, a]))
+            if i is not None:
+                res[i, 0] += F1[e, a]
+                res[i, 1] += F3[e, a]
+    return res
+
+
+def residual_at(mesh: MeshP, U, Un, Unm1, p: FGParams, nodes) -> np.ndarray:
+    """Rows of residual() at the listed nodes only (the elements containing them)."""
+    return _rows_at(mesh, U, Un, Unm1, p, nodes)
+
+
+def jvp_at(mesh: MeshP, U, Un, Unm1, v, p: FGParams, nodes) -> np.ndarray:
+    """Rows of jvp() at the listed nodes only (complex step on the local elements)."""
+    return _rows_at(mesh, U, Un, Unm1, p, nodes, v)

@@ -133,3 +133,23 @@ def test_q2_complex_step_jacobian_vs_central_differences():
     v = rng.standard_normal((m.n_nodes, 2))
     np.testing.assert_allclose(fg.jvp(m, U, Un, Unm1, v, P).reshape(-1), J @ v.reshape(-1), rtol=0,
                                atol=1e-12 * np.abs(J).max() * np.abs(v).max() * 10)
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 1)])
+def test_local_rows_equal_full_residual_and_tangent(dim, order):
+    """residual_at / jvp_at (the elements around the listed nodes only; a node on
+    an element boundary along an axis lies in two elements, any other in one)
+    reproduce the rows of the full assembly."""
+    n, L = ((7, 5), (2.8, 2.0)) if dim == 2 else ((4, 3, 3), (1.6, 1.2, 1.2))
+    m = fg.MeshP(dim, n, L, order)
+    P = fg.FGParams(dt=1e-3, eps4=0.02, beta=50.0, Gamma=0.02, W=0.5, alpha=4.0, Lcp=1.0,
+                            Tm=1.0, theta=0.6)
+    rngs = [np.random.default_rng(s) for s in (4, 5, 6, 7)]
+    U, Un, Unm1, v = (np.stack([r.uniform(0, 1, m.n_nodes), r.uniform(-1, 1, m.n_nodes)], axis=1)
+                      for r in rngs)
+    nodes = np.array(sorted({0, 1, 2, m.nn[0], m.nn[0] + 1, m.n_nodes // 2, m.n_nodes // 2 + 1,
+                             m.n_nodes - 2, m.n_nodes - 1}))
+    F = fg.residual(m, U, Un, Unm1, P)
+    J = fg.jvp(m, U, Un, Unm1, v, P)
+    assert np.abs(fg.residual_at(m, U, Un, Unm1, P, nodes) - F[nodes]).max() < 1e-13 * np.abs(F).max()
+    assert np.abs(fg.jvp_at(m, U, Un, Unm1, v, P, nodes) - J[nodes]).max() < 1e-13 * np.abs(J).max()
