@@ -183,11 +183,17 @@ int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w
            double* gU, double* gUprev, double* gparams, void* stream);
 
 /* [async] Build the preconditioner of Eq. pre at the state U: the blocks
- * M11 = (1/dt)(c psi_j, psi_i) + (c grad psi_j, grad psi_i) with c the cell
- * mean of a(grad phi)^2 (Eqs. m11, pref2 with k = 1) and
- * M22 = (1/dt)(psi_j, psi_i) + D (grad psi_j, grad psi_i) (Eqs. m22,
+ * M11 = (1/dt)(c psi_j, psi_i) + theta (c grad psi_j, grad psi_i) with c the
+ * cell mean of a(grad phi)^2 (Eqs. m11, pref2 with k = 1) and
+ * M22 = (1/dt)(psi_j, psi_i) + theta D (grad psi_j, grad psi_i) (Eqs. m22,
  * preconc2).  kind: PF_PC_NONE, PF_PC_JACOBI, PF_PC_GMG; precision PF_FP64 or
- * PF_FP32 (the GMG V-cycle's arithmetic; Jacobi is always FP64). */
+ * PF_FP32 (the GMG V-cycle's arithmetic; Jacobi is always FP64).  The first
+ * GMG set-up of a precision allocates its level hierarchy (about 1.2 x 5
+ * vectors of the grid in that precision, plus the cell coefficients and the
+ * diagonal) and may return PF_ERR_OOM.  The environment variable
+ * PF_GMG_TILE_GROUPS (a positive integer, read at that allocation) sets the
+ * workgroup target of the tiled 3-D smoothers' z-march (default 4096); it
+ * changes the work split, not the result. */
 int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, void* stream);
 
 /* [async] z = M^-1 r with the preconditioner of the last pf_precond_setup
