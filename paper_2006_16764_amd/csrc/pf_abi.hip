@@ -169,17 +169,14 @@ int check_opts(const pf_problem* pb, const pf_solver_opts* o) {
   return PF_OK;
 }
 
-// Copy n doubles from device to the pinned staging buffer and wait.
-int fetch(pf_problem* pb, const double* dev, int n, hipStream_t s) {
-  PF_HIP_CHECK(hipMemcpyAsync(pb->host_pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  PF_HIP_CHECK(hipStreamSynchronize(s));
-  return PF_OK;
-}
 
+// |x|: the reduction also writes its result into mapped host memory, so the
+// host reads it after the stream syncs without a copy.
 int norm2(pf_problem* pb, const double* x, double* out, hipStream_t s) {
-  PF_TRY(blas_multidot(pb, x, pb->n_dof, 1, x, pb->n_dof, pb->red_out + 250, s));
-  PF_TRY(fetch(pb, pb->red_out + 250, 1, s));
-  *out = std::sqrt(pb->host_pinned[0]);
+  PF_TRY(blas_multidot(pb, x, pb->n_dof, 1, x, pb->n_dof, pb->red_out + 250, s,
+                       pb->host_pinned_dev + 250));
+  PF_HIP_CHECK(hipStreamSynchronize(s));
+  *out = std::sqrt(pb->host_pinned[250]);
   return PF_OK;
 }
 
@@ -271,9 +268,8 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   // products of V_{j+1} with V_0..V_{j+1}: its second-projection
   // coefficients sv[0..j] and its norm after that projection
   auto finish_products = [&](int j, double* rho_out) -> int {
-    PF_TRY(blas_multidot(pb, V, n, j + 2, V + (long long)(j + 1) * n, n, dots_dev, s));
-    PF_HIP_CHECK(hipMemcpyAsync(hp + 512, dots_dev, (j + 2) * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
+    PF_TRY(blas_multidot(pb, V, n, j + 2, V + (long long)(j + 1) * n, n, dots_dev, s,
+                         pb->host_pinned_dev + 512));
     PF_HIP_CHECK(hipStreamSynchronize(s));
     double ssq = 0.0;
     for (int k = 0; k <= j; ++k) {
@@ -299,9 +295,7 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
       double* w = V + (long long)(j + 1) * n;
       PF_TRY(pc_apply(pb, vj, zj, s));
       PF_TRY(op.apply(zj, w, s));
-      PF_TRY(blas_dcgs_dots(pb, V, n, j, n, dots_dev, s));
-      PF_HIP_CHECK(hipMemcpyAsync(hp + 512, dots_dev, (2 * j + 3) * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
+      PF_TRY(blas_dcgs_dots(pb, V, n, j, n, dots_dev, s, pb->host_pinned_dev + 512));
       PF_HIP_CHECK(hipStreamSynchronize(s));
       const double* dt = hp + 512;          // V_k . V_j (k < j), |V_j|^2
       const double* dw = hp + 512 + j + 1;  // V_k . w (k < j), V_j . w, |w|^2
@@ -756,7 +750,10 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   if (hipMalloc(&pb->red_partials, (size_t)kRedRows * pb->n_red_blocks * sizeof(double)) !=
           hipSuccess ||
       hipMalloc(&pb->red_out, 1024 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&pb->host_pinned, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&pb->host_pinned, 1024 * sizeof(double),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&pb->host_pinned_dev), pb->host_pinned, 0) !=
+          hipSuccess ||
       hipMalloc(&pb->elem_buf, (size_t)pb->elem_buf_len * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->side_buf, (size_t)pb->side_len * sizeof(double)) != hipSuccess ||
       hipMalloc(&pb->vjp_partials, (size_t)2 * pb->n_elem_blocks * sizeof(double)) != hipSuccess ||

@@ -69,16 +69,20 @@ __global__ void __launch_bounds__(kRedThreads)
 }
 
 // out[j] = scale * sum_b partials[j * nparts + b], fixed order per thread then
-// fixed block butterfly; one block per j.
+// fixed block butterfly; one block per j.  out_host (may be NULL): the same
+// values into mapped host memory, read by the host after the stream syncs.
 __global__ void __launch_bounds__(kRedThreads)
     k_reduce(const double* __restrict__ partials, int nparts, double* __restrict__ out,
-             double scale) {
+             double scale, double* __restrict__ out_host) {
   __shared__ double sh[kRedThreads / 64];
   const int j = blockIdx.x;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nparts; b += kRedThreads) acc += partials[(long long)j * nparts + b];
   const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[j] = scale * t;
+  if (threadIdx.x == 0) {
+    out[j] = scale * t;
+    if (out_host) out_host[j] = scale * t;
+  }
 }
 
 // x[i] += sum_j coef[j] * V_j[i]  (runtime k, coefficients on the device)
@@ -245,14 +249,15 @@ unsigned grid_for(long long n2, int threads, unsigned cap) {
 }  // namespace
 
 int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const double* w,
-                  long long n, double* out_dev, hipStream_t s) {
+                  long long n, double* out_dev, hipStream_t s, double* out_host) {
   if (k <= 0) return PF_OK;
   const int nb = pb->n_red_blocks;
   const int chunks = (k + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(k_multidot, dim3(nb, chunks), dim3(kRedThreads), 0, s, V, ld, k, w, n,
                      pb->red_partials);
   PF_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, s, pb->red_partials, nb, out_dev, 1.0);
+  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, s, pb->red_partials, nb, out_dev, 1.0,
+                     out_host);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }
@@ -263,7 +268,7 @@ int blas_dot(pf_problem* pb, const double* x, const double* y, long long n, doub
 }
 
 int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long long n,
-                   double* out_dev, hipStream_t s) {
+                   double* out_dev, hipStream_t s, double* out_host) {
   if (j < 0 || 2 * j + 3 > kRedRows) return PF_ERR_INVALID_ARG;
   const int nb = pb->n_red_blocks;
   if (j <= 8) {
@@ -278,7 +283,7 @@ int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long lo
   }
   PF_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_reduce, dim3(2 * j + 3), dim3(kRedThreads), 0, s, pb->red_partials, nb,
-                     out_dev, 1.0);
+                     out_dev, 1.0, out_host);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }
@@ -337,7 +342,8 @@ int blas_fd_eps_cached(pf_problem* pb, const double* unorm2_dev, const double* v
 
 int blas_reduce_partials(const double* partials, int nparts, int k, double* out_dev, double scale,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, s, partials, nparts, out_dev, scale);
+  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, s, partials, nparts, out_dev, scale,
+                     nullptr);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

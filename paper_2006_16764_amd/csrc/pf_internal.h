@@ -134,8 +134,10 @@ long long fg_elem_buf_len(const pf_problem* pb);
 // Deterministic reductions over n doubles: fixed grid, fixed order.
 int blas_dot(pf_problem* pb, const double* x, const double* y, long long n, double* out_dev,
              hipStream_t s);
+// out_host (device alias of mapped host memory, may be NULL) receives a copy
+// of the results for the host, valid once the stream has synchronised.
 int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const double* w,
-                  long long n, double* out_dev, hipStream_t s);
+                  long long n, double* out_dev, hipStream_t s, double* out_host = nullptr);
 // Rows of the reduction workspace (red_partials holds kRedRows * n_red_blocks).
 constexpr int kRedRows = 128;
 // One Gram-Schmidt step with a delayed second projection (t = V_j, w = V_{j+1}):
@@ -143,7 +145,7 @@ constexpr int kRedRows = 128;
 // in-place updates t <- (t - V_{<j} s) inv_rho, w <- (w - V_{<j} h - hj t) inv_eta with
 // s = out[0..j-1] and h = out[j+1..2j] of that product sweep (left on the device).
 int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long long n,
-                   double* out_dev, hipStream_t s);
+                   double* out_dev, hipStream_t s, double* out_host = nullptr);
 int blas_dcgs_update(double* V, long long ld, int j, const double* dots_dev, double hj,
                      double inv_rho, double inv_eta, long long n, hipStream_t s);
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
@@ -190,7 +192,8 @@ struct pf_problem {
   int n_red_blocks;
   double* red_partials;  // kRedRows * n_red_blocks
   double* red_out;       // 1024 doubles of device results
-  double* host_pinned;   // 1024 doubles of pinned host staging
+  double* host_pinned;   // 1024 doubles of pinned, mapped host staging
+  double* host_pinned_dev;  // its device alias (reductions write results there)
 
   // residual-family scratch
   double* elem_buf;      // element contributions (element pass)
