@@ -173,10 +173,10 @@ int check_opts(const pf_problem* pb, const pf_solver_opts* o) {
 // |x|: the reduction also writes its result into mapped host memory, so the
 // host reads it after the stream syncs without a copy.
 int norm2(pf_problem* pb, const double* x, double* out, hipStream_t s) {
-  PF_TRY(blas_multidot(pb, x, pb->n_dof, 1, x, pb->n_dof, pb->red_out + 250, s,
-                       pb->host_pinned_dev + 250));
+  PF_TRY(blas_multidot(pb, x, pb->n_dof, 1, x, pb->n_dof, pb->red_out + kSlotNorm, s,
+                       pb->host_pinned_dev + kSlotNorm));
   PF_HIP_CHECK(hipStreamSynchronize(s));
-  *out = std::sqrt(pb->host_pinned[250]);
+  *out = std::sqrt(pb->host_pinned[kSlotNorm]);
   return PF_OK;
 }
 
@@ -190,7 +190,7 @@ struct Op {
   const double* unorm2 = nullptr;  // |U|^2 on the device (FD), computed by prepare()
   int prepare(hipStream_t s) {
     if (kind != 0) return PF_OK;
-    double* d = pb->red_out + 203;
+    double* d = pb->red_out + kSlotUnorm;
     PF_TRY(blas_multidot(pb, U, pb->n_dof, 1, U, pb->n_dof, d, s));
     unorm2 = d;
     return PF_OK;
@@ -228,8 +228,8 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   double* V = pb->V;
   double* Z = pb->Z;
   double* r = pb->tmp_vec[3];
-  double* ydev = pb->red_out + 300;
-  double* dots_dev = pb->red_out + 512;
+  double* ydev = pb->red_out + kSlotY;
+  double* dots_dev = pb->red_out + kSlotDots;
   double* hp = pb->host_pinned;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   std::vector<double> hcol(m + 1), sv(m + 1), col(m + 1);
@@ -269,14 +269,14 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   // coefficients sv[0..j] and its norm after that projection
   auto finish_products = [&](int j, double* rho_out) -> int {
     PF_TRY(blas_multidot(pb, V, n, j + 2, V + (long long)(j + 1) * n, n, dots_dev, s,
-                         pb->host_pinned_dev + 512));
+                         pb->host_pinned_dev + kSlotDots));
     PF_HIP_CHECK(hipStreamSynchronize(s));
     double ssq = 0.0;
     for (int k = 0; k <= j; ++k) {
-      sv[k] = hp[512 + k];
+      sv[k] = hp[kSlotDots + k];
       ssq += sv[k] * sv[k];
     }
-    const double r2 = hp[512 + j + 1] - ssq;
+    const double r2 = hp[kSlotDots + j + 1] - ssq;
     *rho_out = r2 > 0.0 ? std::sqrt(r2) : 0.0;
     return PF_OK;
   };
@@ -295,10 +295,10 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
       double* w = V + (long long)(j + 1) * n;
       PF_TRY(pc_apply(pb, vj, zj, s));
       PF_TRY(op.apply(zj, w, s));
-      PF_TRY(blas_dcgs_dots(pb, V, n, j, n, dots_dev, s, pb->host_pinned_dev + 512));
+      PF_TRY(blas_dcgs_dots(pb, V, n, j, n, dots_dev, s, pb->host_pinned_dev + kSlotDots));
       PF_HIP_CHECK(hipStreamSynchronize(s));
-      const double* dt = hp + 512;          // V_k . V_j (k < j), |V_j|^2
-      const double* dw = hp + 512 + j + 1;  // V_k . w (k < j), V_j . w, |w|^2
+      const double* dt = hp + kSlotDots;    // V_k . V_j (k < j), |V_j|^2
+      const double* dw = hp + kSlotDots + j + 1;  // V_k . w (k < j), V_j . w, |w|^2
       // finish V_j: second projection coefficients dt[0..j-1], norm rho
       double rho = 1.0;
       if (j > 0) {
@@ -388,8 +388,8 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
       for (int k = i + 1; k < jend; ++k) t -= H[i * m + k] * y[k];
       y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
     }
-    std::memcpy(pb->host_pinned + 160, y.data(), jend * sizeof(double));
-    PF_HIP_CHECK(hipMemcpyAsync(ydev, pb->host_pinned + 160, jend * sizeof(double),
+    std::memcpy(pb->host_pinned + kSlotHostY, y.data(), jend * sizeof(double));
+    PF_HIP_CHECK(hipMemcpyAsync(ydev, pb->host_pinned + kSlotHostY, jend * sizeof(double),
                                 hipMemcpyHostToDevice, s));
     PF_TRY(blas_combine(pb, Z, n, jend, ydev, x, n, s));
     PF_HIP_CHECK(hipStreamSynchronize(s));
@@ -724,7 +724,7 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   }
   *out = nullptr;
   PF_TRY(check_params(params));
-  if (gmres_m_max < 1 || gmres_m_max > 60) {
+  if (gmres_m_max < 1 || gmres_m_max > kMaxGmresM) {
     set_error("gmres_m_max must be in [1, 60]");
     return PF_ERR_INVALID_ARG;
   }
@@ -749,8 +749,8 @@ int pf_create(const pf_params* params, int gmres_m_max, pf_problem** out) {
   pb->side_len = pb->geo.dim == 3 ? fused3_side_len(pb->geo) : 1;
   if (hipMalloc(&pb->red_partials, (size_t)kRedRows * pb->n_red_blocks * sizeof(double)) !=
           hipSuccess ||
-      hipMalloc(&pb->red_out, 1024 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&pb->host_pinned, 1024 * sizeof(double),
+      hipMalloc(&pb->red_out, kRedSlots * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&pb->host_pinned, kRedSlots * sizeof(double),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer(reinterpret_cast<void**>(&pb->host_pinned_dev), pb->host_pinned, 0) !=
           hipSuccess ||
@@ -1081,7 +1081,7 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   }
   if (rc != PF_OK) return rc;
   double* gP = pb->tmp_vec[4];
-  double* gp_local = pb->red_out + 400;
+  double* gp_local = pb->red_out + kSlotParams;
   PF_TRY(launch_residual_family(pb, MODE_VJP, U, Uprev, lam, nullptr, nullptr, nullptr, gP,
                                 pb->vjp_partials, s));
   PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gp_local, 1.0, s));

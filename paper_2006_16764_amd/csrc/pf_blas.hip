@@ -323,7 +323,7 @@ int blas_axpby(double a, const double* x, double b, const double* y, double* z, 
 
 int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, double* eps_dev,
                 hipStream_t s) {
-  double* nrm = pb->red_out + 200;
+  double* nrm = pb->red_out + kSlotFdU;
   PF_TRY(blas_multidot(pb, U, n, 1, U, n, nrm, s));
   PF_TRY(blas_multidot(pb, v, n, 1, v, n, nrm + 1, s));
   hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, nrm, nrm + 1, eps_dev);
@@ -333,7 +333,7 @@ int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, d
 
 int blas_fd_eps_cached(pf_problem* pb, const double* unorm2_dev, const double* v, long long n,
                        double* eps_dev, hipStream_t s) {
-  double* nv = pb->red_out + 201;
+  double* nv = pb->red_out + kSlotFdV;
   PF_TRY(blas_multidot(pb, v, n, 1, v, n, nv, s));
   hipLaunchKernelGGL(k_fd_eps, dim3(1), dim3(1), 0, s, unorm2_dev, nv, eps_dev);
   PF_HIP_CHECK(hipGetLastError());

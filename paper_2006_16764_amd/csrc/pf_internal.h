@@ -140,6 +140,23 @@ int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const do
                   long long n, double* out_dev, hipStream_t s, double* out_host = nullptr);
 // Rows of the reduction workspace (red_partials holds kRedRows * n_red_blocks).
 constexpr int kRedRows = 128;
+
+// Slots of the handle's 1024-double result arrays: red_out on the device and
+// host_pinned (mapped host memory, written by reductions the host waits for).
+constexpr int kMaxGmresM = 60;  // largest gmres_m_max pf_create accepts
+constexpr int kRedSlots = 1024;
+constexpr int kSlotFdU = 200;   // red_out: |U|^2 of the FD step size (one-off form)
+constexpr int kSlotFdV = 201;   // red_out: |v|^2 of the FD step size
+constexpr int kSlotUnorm = 203; // red_out: |U|^2 kept for the FD operator of a Krylov solve
+constexpr int kSlotNorm = 250;  // red_out and host_pinned: |x|^2 of a norm the host reads
+constexpr int kSlotHostY = 160; // host_pinned: staging of the FGMRES combination y
+constexpr int kSlotY = 300;     // red_out: the FGMRES combination y (<= kMaxGmresM)
+constexpr int kSlotParams = 400;  // red_out: the two parameter sums of a VJP
+constexpr int kSlotDots = 512;  // red_out and host_pinned: Gram-Schmidt products (<= 2m + 3)
+static_assert(kSlotHostY + kMaxGmresM <= kSlotNorm, "host y staging overlaps the norm slot");
+static_assert(kSlotY + kMaxGmresM <= kSlotParams, "y overlaps the parameter sums");
+static_assert(kSlotDots + 2 * kMaxGmresM + 3 <= kRedSlots, "Gram-Schmidt products overflow");
+static_assert(2 * kMaxGmresM + 3 <= kRedRows, "Gram-Schmidt products exceed the reduction rows");
 // One Gram-Schmidt step with a delayed second projection (t = V_j, w = V_{j+1}):
 // out[0..2j+2] = V_{<j}^T t, t.t, V_{<j}^T w, t.w, w.w in one sweep; then the
 // in-place updates t <- (t - V_{<j} s) inv_rho, w <- (w - V_{<j} h - hj t) inv_eta with
@@ -191,8 +208,8 @@ struct pf_problem {
   // reduction scratch: partial sums [k][n_red_blocks] and results
   int n_red_blocks;
   double* red_partials;  // kRedRows * n_red_blocks
-  double* red_out;       // 1024 doubles of device results
-  double* host_pinned;   // 1024 doubles of pinned, mapped host staging
+  double* red_out;       // kRedSlots doubles of device results
+  double* host_pinned;   // kRedSlots doubles of pinned, mapped host staging
   double* host_pinned_dev;  // its device alias (reductions write results there)
 
   // residual-family scratch
