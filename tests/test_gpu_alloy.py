@@ -50,7 +50,9 @@ def make(dim, n, L, p):
 
 
 P = AlloyParams(dt=0.05, eps4=0.03, lam=4.0, D=3.0, k=0.2, l_T=6.0, x_iso=0.7, v_pull=1.3, theta=0.5)
-CASES = [(2, (40, 13), (16.0, 5.2)), (3, (13, 11, 9), (5.2, 4.4, 3.6)), (3, (18, 17, 5), (7.2, 6.8, 2.0))]
+CASES = [(2, (40, 13), (16.0, 5.2)), (3, (13, 11, 9), (5.2, 4.4, 3.6)), (3, (18, 17, 5), (7.2, 6.8, 2.0)),
+         # degenerate: one element, one element across, one element layer
+         (3, (1, 1, 1), (0.4, 0.4, 0.4)), (2, (1, 6), (0.4, 2.4)), (3, (17, 2, 1), (6.8, 0.8, 0.4))]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")

@@ -53,7 +53,10 @@ def make(dim, n, L, order, p):
 
 
 CASES = [(2, (37, 23), (7.4, 4.6), 1), (3, (9, 7, 6), (3.6, 2.8, 2.4), 1), (2, (13, 9), (5.2, 3.6), 2),
-         (2, (16, 16), (6.4, 6.4), 2)]
+         (2, (16, 16), (6.4, 6.4), 2),
+         # degenerate: one element (Q1, Q2), one element across (Q1 3-D, Q2)
+         (2, (1, 1), (0.4, 0.4), 1), (3, (1, 2, 1), (0.4, 0.8, 0.4), 1), (2, (1, 1), (0.4, 0.4), 2),
+         (2, (1, 5), (0.4, 2.0), 2), (2, (17, 1), (6.8, 0.4), 2)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"q{c[3]}-{c[0]}d-{'x'.join(map(str, c[1]))}")
