@@ -86,6 +86,10 @@ def flops_per_element(dim):
 # because the compiler folds the constant point weights of the unrolled rows;
 # the executed count is the conservative one.  2-D: the source-level count.
 FLOPS_PER_ELEM = {3: 3128, 2: flops_per_element(2)}
+# The same counter for every 3-D element kernel of the residual family
+# (k_fused3<0..3>: residual, FD Jv, analytic Jv, VJP with all outputs), for the
+# per-kernel FP64 rates reported beside the roofline.
+KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3128, "fd_jv": 3039, "analytic_jv": 5101, "vjp": 6870}
 BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
 # HBM bytes moved by one pf_residual call (k_fused3<0> + k_fixup3<0>) on the
@@ -295,6 +299,10 @@ def main():
                        "vjp": round(t_vjp, 4), "vcycle_fp32": round(t_pc32, 4), "vcycle_fp64": round(t_pc64, 4)},
         "kernels_mdofs": {k: round(n / (v * 1e-3) / 1e6, 1) for k, v in
                           (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv), ("vjp", t_vjp))},
+        "kernels_fp64": ({k: {"tflops": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12, 2),
+                              "frac": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12 / peak, 3)}
+                          for k, v in (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv),
+                                       ("vjp", t_vjp))} if w.dim == 3 else None),
         "newton": [{"its": s["newton_its"], "gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)}
                    for s in newton],
         "adjoint": [{"gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)} for s in adj],
