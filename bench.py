@@ -123,6 +123,37 @@ def residual_traffic(workload_name):
     return t["bytes"]
 
 
+def vcycle_bytes(dim, n, s):
+    """Algorithmic HBM bytes of one V-cycle (both blocks, element size s = 4
+    for FP32, 8 for FP64) on a cubic mesh of n elements per side: every array a
+    kernel touches is counted once per node (cell arrays as one entry per node).
+
+    Finest level, per node: the fused zero-start two steps read the FP64
+    right-hand side (16 B), the stored phi-block diagonal and the cell
+    coefficients (s each) and write the working right-hand side and the
+    iterate (2s each): 16 + 6s; the residual reads iterate, coefficients and
+    right-hand side and writes the residual: 7s; restriction reads the residual
+    and writes the coarse right-hand side: 2s + 2s/8; prolongation reads the
+    coarse correction and reads and writes the iterate: 2s/8 + 4s; the first
+    post-smoothing step reads iterate, coefficients, right-hand side and writes
+    iterate and direction: 9s; the last reads the direction too and writes the
+    FP64 result (16 B): 7s + 16.  Total 32 + 35.5s.
+    Coarser levels: the zero-start steps read the right-hand side, diagonal and
+    coefficients and write the iterate (6s); the last post step writes the
+    iterate instead of the FP64 result (9s).  Total 37.5s.  Coarsest grid:
+    coefficients, right-hand side, iterate (5s).  Levels halve while every side
+    is even and longer than 4 elements, as the hierarchy does."""
+    sizes = [n]
+    while n % 2 == 0 and n > 4:
+        n //= 2
+        sizes.append(n)
+    nodes = [(m + 1) ** dim for m in sizes]
+    total = (32 + 35.5 * s) * nodes[0]
+    total += sum(37.5 * s * k for k in nodes[1:-1])
+    total += 5 * s * nodes[-1]
+    return total
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -303,6 +334,10 @@ def main():
                               "frac": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12 / peak, 3)}
                           for k, v in (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv),
                                        ("vjp", t_vjp))} if w.dim == 3 else None),
+        "vcycle_hbm": {name: {"bytes": int(vb), "gbs": round(vb / (t * 1e-3) / 1e9, 1),
+                              "frac": round(vb / (t * 1e-3) / 8e12, 3)}
+                       for name, vb, t in (("fp32", vcycle_bytes(w.dim, w.n, 4), t_pc32),
+                                           ("fp64", vcycle_bytes(w.dim, w.n, 8), t_pc64))},
         "newton": [{"its": s["newton_its"], "gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)}
                    for s in newton],
         "adjoint": [{"gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)} for s in adj],
