@@ -73,7 +73,10 @@ extern "C" {
 
 /* Model and mesh.  dim = 2 or 3; n[k] >= 1 elements per axis (n[2] ignored
  * in 2-D); half_width[k] > 0.  dt > 0, D > 0, delta2 > 0 (regularises the
- * anisotropy where grad phi = 0; 1e-16 is the default reading); theta in
+ * anisotropy where grad phi = 0; 1e-16 is the default reading.  Where grad phi
+ * vanishes identically in an element, a gradient perturbation above
+ * sqrt(delta2) moves a by O(eps4), so FD products or the FP32 V-cycle can stall
+ * Newton at such exactly symmetric states); theta in
  * (0, 1]: the time weight of Eq. dpf (1 backward Euler, 1/2 the trapezoidal
  * or Crank-Nicolson rule).  order: Lagrange element order, 1 (bilinear /
  * trilinear; 0 is read as 1) or 2 (biquadratic, 2-D, free-growth model only):
