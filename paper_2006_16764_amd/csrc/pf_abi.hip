@@ -463,10 +463,9 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
   double* F = pb->tmp_vec[0];
   double* dU = pb->tmp_vec[1];
   double* Ut = pb->tmp_vec[2];
-  double* rhs = pb->tmp_vec[3] + 0;  // reused as FGMRES restart vector only after rhs is consumed
+  // tmp_vec[3] is FGMRES's restart vector
   double* Ft = pb->tmp_vec[4];
   double* B = pb->tmp_vec[5];
-  (void)rhs;
   double* coef = pc_coef_buffer(pb);
   // |X + load|, staged through B (free outside the linear solve)
   auto norm_loaded = [&](const double* X, double* out) -> int {
