@@ -48,7 +48,9 @@ class PhaseFieldEvolve(torch.autograd.Function):
         pb.set_params(ctx.params)
         n = pb.n_dof
         S = states.view(K + 1, n)
-        mu = grad_UK.reshape(-1).contiguous().to(torch.float64)
+        # a copy: the two adjoint buffers are swapped and overwritten step by
+        # step, and the incoming gradient belongs to the caller
+        mu = grad_UK.reshape(-1).to(torch.float64).clone()
         lam, mu_prev = pb.new_vector(), pb.new_vector()
         gp = torch.zeros(2, dtype=torch.float64, device=states.device)
         for k in range(K, 0, -1):

@@ -176,6 +176,38 @@ def test_adjoint_gradient_matches_oracle():
     assert abs(g[1] - gl_ref) < 1e-6 * abs(gl_ref) + 1e-12, (g, ge_ref, gl_ref)
 
 
+def test_autograd_backward_matches_the_adjoint_sweep_and_keeps_its_input():
+    """The autograd Function's backward is the adjoint sweep above, and it
+    leaves the caller's incoming gradient untouched (its two adjoint buffers
+    are swapped and overwritten step by step)."""
+    note("autograd backward")
+    from paper_2006_16764_amd import binding, evolve
+    w, mesh, p, U0, pb = seed_problem("adjoint2d_512", 16)
+    steps = 3
+    opts = binding.default_opts(tau_r=1e-12)
+    e = torch.tensor(p.eps4, dtype=torch.float64, requires_grad=True)
+    l = torch.tensor(p.lam, dtype=torch.float64, requires_grad=True)
+    UK = evolve.evolve(e, l, dev(U0), pb, steps, opts)
+    g = dev(inputs.random_vector(mesh.n_nodes, 21))
+    g0 = g.clone()
+    UK.backward(gradient=g)
+    assert torch.equal(g, g0)
+    states = torch.zeros((steps + 1) * pb.n_dof, dtype=torch.float64, device="cuda")
+    states[: pb.n_dof] = dev(U0)
+    pb.pf_evolve(states, steps, opts)
+    S = states.view(steps + 1, -1)
+    assert torch.equal(S[steps], UK.detach())
+    gp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    mu, lam, mu_prev = g.clone(), pb.new_vector(), pb.new_vector()
+    for k in range(steps, 0, -1):
+        pb.pf_adjoint_step(S[k], S[k - 1], mu, lam, mu_prev, gp, opts)
+        mu, mu_prev = mu_prev, mu
+    ref = gp.cpu().numpy()
+    assert abs(e.grad.item() - ref[0]) <= 1e-12 * abs(ref[0])
+    assert abs(l.grad.item() - ref[1]) <= 1e-12 * abs(ref[1]) + 1e-300
+    assert pb.close() == 0
+
+
 # ---------------------------------------------------------------- failure paths (forced from the host)
 def test_nonfinite_state_is_reported():
     note("nonfinite")
