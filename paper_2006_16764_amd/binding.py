@@ -160,11 +160,16 @@ def _check(code: int, fn: str):
         raise PFError(code, fn, load().pf_last_error().decode())
 
 
-def _ptr(t: Optional[torch.Tensor]):
+def _ptr(t: Optional[torch.Tensor], n: int = 0):
+    """Device address of t (None passes through).  The library takes plain
+    pointers, so the sizes it will touch are checked here: t must hold at least
+    n float64 entries."""
     if t is None:
         return None
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 CUDA tensor")
+    if t.numel() < n:
+        raise ValueError(f"tensor of {t.numel()} entries where {n} are needed")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -223,6 +228,10 @@ class Problem:
         except Exception:
             pass
 
+    def _v(self, t, n=None):
+        """_ptr of a vector argument: 2 * n_nodes entries unless n says otherwise."""
+        return _ptr(t, self.n_dof if n is None else n)
+
     def new_vector(self, device="cuda") -> torch.Tensor:
         return torch.empty(self.n_dof, dtype=torch.float64, device=device)
 
@@ -231,43 +240,44 @@ class Problem:
         self.params = params
 
     def pf_residual(self, U, Uprev, F, stream=None):
-        _check(load().pf_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(F), _stream(stream)), "pf_residual")
+        _check(load().pf_residual(self.h, self._v(U), self._v(Uprev), self._v(F), _stream(stream)),
+               "pf_residual")
         return F
 
     def pf_theta_explicit(self, Uprev, Uprev2, E, stream=None):
-        _check(load().pf_theta_explicit(self.h, _ptr(Uprev), _ptr(Uprev2), _ptr(E), _stream(stream)),
+        _check(load().pf_theta_explicit(self.h, self._v(Uprev), self._v(Uprev2), self._v(E), _stream(stream)),
                "pf_theta_explicit")
         return E
 
     def pf_jvp(self, U, Uprev, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
-        _check(load().pf_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(v), _ptr(F0), mode, _ptr(Jv),
+        _check(load().pf_jvp(self.h, self._v(U), self._v(Uprev), self._v(v), self._v(F0), mode, self._v(Jv),
                              _stream(stream)), "pf_jvp")
         return Jv
 
     def pf_vjp(self, U, Uprev, w, gU=None, gUprev=None, gparams=None, stream=None):
-        _check(load().pf_vjp(self.h, _ptr(U), _ptr(Uprev), _ptr(w), _ptr(gU), _ptr(gUprev),
-                             _ptr(gparams), _stream(stream)), "pf_vjp")
+        _check(load().pf_vjp(self.h, self._v(U), self._v(Uprev), self._v(w), self._v(gU), self._v(gUprev),
+                             self._v(gparams, 2), _stream(stream)), "pf_vjp")
 
     def pf_precond_setup(self, U, kind=PF_PC_GMG, precision=PF_FP64, stream=None):
-        _check(load().pf_precond_setup(self.h, _ptr(U), kind, precision, _stream(stream)),
+        _check(load().pf_precond_setup(self.h, self._v(U), kind, precision, _stream(stream)),
                "pf_precond_setup")
 
     def pf_precond_apply(self, r, z, stream=None):
-        _check(load().pf_precond_apply(self.h, _ptr(r), _ptr(z), _stream(stream)), "pf_precond_apply")
+        _check(load().pf_precond_apply(self.h, self._v(r), self._v(z), _stream(stream)), "pf_precond_apply")
         return z
 
     def pf_linear_solve(self, U, Uprev, b, x, transpose=0, rtol=1e-10, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        _check(load().pf_linear_solve(self.h, _ptr(U), _ptr(Uprev), _ptr(b), _ptr(x), transpose, rtol,
-                                      ctypes.byref(o), ctypes.byref(st), _stream(stream)),
-               "pf_linear_solve")
+        _check(load().pf_linear_solve(self.h, self._v(U), self._v(Uprev), self._v(b), self._v(x),
+                                      transpose, rtol, ctypes.byref(o), ctypes.byref(st),
+                                      _stream(stream)), "pf_linear_solve")
         return st.as_dict()
 
     def pf_newton_step(self, Uprev, U, opts=None, stream=None, check=True):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        rc = load().pf_newton_step(self.h, _ptr(Uprev), _ptr(U), ctypes.byref(o), ctypes.byref(st),
+        rc = load().pf_newton_step(self.h, self._v(Uprev), self._v(U), ctypes.byref(o), ctypes.byref(st),
                                    _stream(stream))
         if check:
             _check(rc, "pf_newton_step")
@@ -278,7 +288,7 @@ class Problem:
     def pf_newton_step_theta(self, Uprev2, Uprev, U, opts=None, stream=None, check=True):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        rc = load().pf_newton_step_theta(self.h, _ptr(Uprev2), _ptr(Uprev), _ptr(U), ctypes.byref(o),
+        rc = load().pf_newton_step_theta(self.h, self._v(Uprev2), self._v(Uprev), self._v(U), ctypes.byref(o),
                                          ctypes.byref(st), _stream(stream))
         if check:
             _check(rc, "pf_newton_step_theta")
@@ -289,16 +299,16 @@ class Problem:
     def pf_evolve(self, states, steps, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        _check(load().pf_evolve(self.h, _ptr(states), steps, ctypes.byref(o), ctypes.byref(st),
-                                _stream(stream)), "pf_evolve")
+        _check(load().pf_evolve(self.h, self._v(states, (steps + 1) * self.n_dof), steps,
+                                ctypes.byref(o), ctypes.byref(st), _stream(stream)), "pf_evolve")
         return st.as_dict()
 
     def pf_adjoint_step(self, U, Uprev, mu, lam, mu_prev, gparams, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        _check(load().pf_adjoint_step(self.h, _ptr(U), _ptr(Uprev), _ptr(mu), _ptr(lam), _ptr(mu_prev),
-                                      _ptr(gparams), ctypes.byref(o), ctypes.byref(st),
-                                      _stream(stream)), "pf_adjoint_step")
+        _check(load().pf_adjoint_step(self.h, self._v(U), self._v(Uprev), self._v(mu), self._v(lam),
+                                      self._v(mu_prev), self._v(gparams, 2), ctypes.byref(o),
+                                      ctypes.byref(st), _stream(stream)), "pf_adjoint_step")
         return st.as_dict()
 
     def pf_set_alloy(self, alloy: pf_alloy_params):
@@ -306,24 +316,24 @@ class Problem:
         self.alloy = alloy
 
     def pf_alloy_residual(self, U, Uprev, Uprev2, t, F, stream=None):
-        _check(load().pf_alloy_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), float(t), _ptr(F),
-                                        _stream(stream)), "pf_alloy_residual")
+        _check(load().pf_alloy_residual(self.h, self._v(U), self._v(Uprev), self._v(Uprev2), float(t),
+                                        self._v(F), _stream(stream)), "pf_alloy_residual")
         return F
 
     def pf_alloy_explicit(self, Uprev, t_prev, E, stream=None):
-        _check(load().pf_alloy_explicit(self.h, _ptr(Uprev), float(t_prev), _ptr(E), _stream(stream)),
+        _check(load().pf_alloy_explicit(self.h, self._v(Uprev), float(t_prev), self._v(E), _stream(stream)),
                "pf_alloy_explicit")
         return E
 
     def pf_alloy_jvp(self, U, Uprev, Uprev2, t, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
-        _check(load().pf_alloy_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), float(t), _ptr(v),
-                                   _ptr(F0), mode, _ptr(Jv), _stream(stream)), "pf_alloy_jvp")
+        _check(load().pf_alloy_jvp(self.h, self._v(U), self._v(Uprev), self._v(Uprev2), float(t), self._v(v),
+                                   self._v(F0), mode, self._v(Jv), _stream(stream)), "pf_alloy_jvp")
         return Jv
 
     def pf_alloy_step(self, Uprev2, Uprev, t_prev, U, opts=None, stream=None, check=True):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        rc = load().pf_alloy_step(self.h, _ptr(Uprev2), _ptr(Uprev), float(t_prev), _ptr(U),
+        rc = load().pf_alloy_step(self.h, self._v(Uprev2), self._v(Uprev), float(t_prev), self._v(U),
                                   ctypes.byref(o), ctypes.byref(st), _stream(stream))
         if check:
             _check(rc, "pf_alloy_step")
@@ -334,8 +344,9 @@ class Problem:
     def pf_alloy_evolve(self, states, steps, t0=0.0, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        _check(load().pf_alloy_evolve(self.h, _ptr(states), steps, float(t0), ctypes.byref(o),
-                                      ctypes.byref(st), _stream(stream)), "pf_alloy_evolve")
+        _check(load().pf_alloy_evolve(self.h, self._v(states, (steps + 1) * self.n_dof), steps,
+                                      float(t0), ctypes.byref(o), ctypes.byref(st), _stream(stream)),
+               "pf_alloy_evolve")
         return st.as_dict()
 
     def pf_set_freegrowth(self, fgp: pf_freegrowth_params):
@@ -343,23 +354,23 @@ class Problem:
         self.fg = fgp
 
     def pf_fg_residual(self, U, Uprev, Uprev2, F, stream=None):
-        _check(load().pf_fg_residual(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), _ptr(F),
+        _check(load().pf_fg_residual(self.h, self._v(U), self._v(Uprev), self._v(Uprev2), self._v(F),
                                      _stream(stream)), "pf_fg_residual")
         return F
 
     def pf_fg_explicit(self, Uprev, E, stream=None):
-        _check(load().pf_fg_explicit(self.h, _ptr(Uprev), _ptr(E), _stream(stream)), "pf_fg_explicit")
+        _check(load().pf_fg_explicit(self.h, self._v(Uprev), self._v(E), _stream(stream)), "pf_fg_explicit")
         return E
 
     def pf_fg_jvp(self, U, Uprev, Uprev2, v, Jv, mode=PF_JV_ANALYTIC, F0=None, stream=None):
-        _check(load().pf_fg_jvp(self.h, _ptr(U), _ptr(Uprev), _ptr(Uprev2), _ptr(v), _ptr(F0), mode,
-                                _ptr(Jv), _stream(stream)), "pf_fg_jvp")
+        _check(load().pf_fg_jvp(self.h, self._v(U), self._v(Uprev), self._v(Uprev2), self._v(v),
+                                self._v(F0), mode, self._v(Jv), _stream(stream)), "pf_fg_jvp")
         return Jv
 
     def pf_fg_step(self, Uprev2, Uprev, U, opts=None, stream=None, check=True):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        rc = load().pf_fg_step(self.h, _ptr(Uprev2), _ptr(Uprev), _ptr(U), ctypes.byref(o),
+        rc = load().pf_fg_step(self.h, self._v(Uprev2), self._v(Uprev), self._v(U), ctypes.byref(o),
                                ctypes.byref(st), _stream(stream))
         if check:
             _check(rc, "pf_fg_step")
@@ -370,16 +381,16 @@ class Problem:
     def pf_fg_evolve(self, states, steps, opts=None, stream=None):
         o = opts if opts is not None else default_opts()
         st = pf_solver_stats()
-        _check(load().pf_fg_evolve(self.h, _ptr(states), steps, ctypes.byref(o), ctypes.byref(st),
-                                   _stream(stream)), "pf_fg_evolve")
+        _check(load().pf_fg_evolve(self.h, self._v(states, (steps + 1) * self.n_dof), steps,
+                                   ctypes.byref(o), ctypes.byref(st), _stream(stream)), "pf_fg_evolve")
         return st.as_dict()
 
     def pf_misfit(self, U, phi_target, L_dev, dLdU=None, stream=None):
-        _check(load().pf_misfit(self.h, _ptr(U), _ptr(phi_target), _ptr(L_dev), _ptr(dLdU),
-                                _stream(stream)), "pf_misfit")
+        _check(load().pf_misfit(self.h, self._v(U), self._v(phi_target, self.n_nodes),
+                                self._v(L_dev, 1), self._v(dLdU), _stream(stream)), "pf_misfit")
 
     def pf_dot(self, x, y, out_dev, stream=None):
-        _check(load().pf_dot(self.h, _ptr(x), _ptr(y), _ptr(out_dev), _stream(stream)), "pf_dot")
+        _check(load().pf_dot(self.h, self._v(x), self._v(y), self._v(out_dev, 1), _stream(stream)), "pf_dot")
 
 
 def problem_for(w, gmres_m_max: int = 30, eps4=None, lam=None, theta=1.0) -> Problem:

@@ -249,3 +249,14 @@ def test_invalid_arguments_are_rejected():
     assert e.value.code == binding.PF_ERR_INVALID_ARG
     lib = binding.load()
     assert lib.pf_residual(pb.h, None, None, None, None) == binding.PF_ERR_INVALID_ARG
+    # the binding checks the sizes the library will touch before calling it
+    short = torch.zeros(pb.n_dof - 2, dtype=torch.float64, device="cuda")
+    F = pb.new_vector()
+    with pytest.raises(ValueError):
+        pb.pf_residual(short, dev(U0), F)
+    with pytest.raises(ValueError):
+        pb.pf_vjp(dev(U0), dev(U0), dev(U0), F, None, torch.zeros(1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        pb.pf_evolve(torch.zeros(pb.n_dof, dtype=torch.float64, device="cuda"), 1)
+    with pytest.raises(ValueError):
+        pb.pf_residual(dev(U0).float(), dev(U0), F)
