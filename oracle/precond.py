@@ -31,10 +31,12 @@ COARSE_DEGREE on [lmin, 1.1 lmax].  The V-cycle takes its steps in this order:
   post-smooth from the corrected iterate.
 
 Pins: V-cycle contraction and symmetry tests; repeated V-cycles converge to the
-direct solve.  The detailed smoother constants are a reading of the paper's
-method, not its text (the paper uses algebraic multigrid and defines no
-geometric one), so the exact V-cycle output is "parity unpinned" beyond those
-properties.
+direct solve; the smoother equals the closed-form Chebyshev error polynomial of
+its interval and the whole cycle equals its closed-form operator
+(I - E) A^-1, E = S (I - P B_c P^T A) S, built from dense matrices.  The
+smoother constants (intervals, degrees, coarsening limit) are a reading of the
+paper's method, not its text (the paper uses algebraic multigrid and defines no
+geometric one): the pins fix the cycle given that reading.
 """
 from __future__ import annotations
 
