@@ -201,7 +201,12 @@ int pf_precond_setup(pf_problem* pb, const double* U, int kind, int precision, v
 
 /* [async] z = M^-1 r with the preconditioner of the last pf_precond_setup
  * (Jacobi: diagonal scaling; GMG: one V-cycle per block).  M^-1 is linear and
- * symmetric.  z must not alias r. */
+ * symmetric.  z must not alias r.  On meshes of at most 2^20 unknowns the
+ * V-cycle is captured once as a HIP graph (on a stream the handle owns) and
+ * replayed between copies into and out of two handle-owned vectors, allocated
+ * on the first such apply (PF_ERR_OOM if they do not fit); the result is the
+ * same bit for bit.  The environment variable PF_GMG_GRAPH=0, read by
+ * pf_create, keeps eager launches. */
 int pf_precond_apply(pf_problem* pb, const double* r, double* z, void* stream);
 
 /* [sync] Solve F'(U) x = b (transpose = 0) or F'(U)^T x = b (transpose = 1)

@@ -81,10 +81,32 @@ struct Hier {
   double* coarse_dev = nullptr;
 };
 
+// A V-cycle captured as one HIP graph: its launches (a few microseconds each on
+// small grids) replay as one submission.  sig holds the block scales the
+// captured kernel arguments were derived from and level0 the hierarchy they
+// point into; either changing forces a new capture.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  double sig[4] = {0.0, 0.0, 0.0, 0.0};
+  const void* level0 = nullptr;
+};
+
+// Meshes up to this many unknowns apply the V-cycle as a replayed graph
+// (measured: a 150^2 free-growth step 20 % faster; at 2.1 M unknowns the two
+// copies cost more than the launches saved).
+constexpr long long kGraphMaxDof = 1LL << 20;
+
 struct PcState {
   Hier<float> h32;
   Hier<double> h64;
   double* coef0 = nullptr;  // FP64 cell coefficient of the phi block (level 0)
+  // graph path (small meshes): fixed input and output vectors of the captured
+  // cycle, the stream it is captured on, one graph per precision
+  bool graph_enabled = true;
+  double* gin = nullptr;
+  double* gout = nullptr;
+  hipStream_t cap = nullptr;
+  GraphCache g32, g64;
 };
 
 __host__ __device__ inline long long nidx(const LvK& g, int i, int j, int k) {
@@ -1373,11 +1395,71 @@ int apply_gmg(pf_problem* pb, Hier<T>& H, const double* r, double* z, hipStream_
   return vcycle<2, T>(pb, H, 0, r, z, s);
 }
 
+// The V-cycle on small meshes: r is copied into the fixed input vector, the
+// cycle captured from gin to gout replays on the caller's stream, and gout is
+// copied to z.  The capture (on the library's own stream, so that the
+// caller's stream may be the null stream) happens on the first apply and again
+// whenever the block scales or the hierarchy change; set-up only rewrites
+// device buffers the graph reads.  The result equals the eager cycle's bit for
+// bit.
+template <class T>
+int apply_gmg_graph(pf_problem* pb, PcState* st, Hier<T>& H, GraphCache& gc, const double* r,
+                    double* z, hipStream_t s) {
+  const long long n = pb->geo.n_nodes;
+  if (!st->gin) {
+    if (hipMalloc(&st->gin, (size_t)2 * n * sizeof(double)) != hipSuccess ||
+        hipMalloc(&st->gout, (size_t)2 * n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("out of device memory for the V-cycle graph vectors");
+      return PF_ERR_OOM;
+    }
+  }
+  if (!st->cap) PF_HIP_CHECK(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
+  double sm[2], sk[2];
+  block_scales(pb, sm, sk);
+  const double sig[4] = {sm[0], sm[1], sk[0], sk[1]};
+  const void* level0 = H.lv.empty() ? nullptr : (const void*)H.lv[0].c;
+  bool same = gc.exec != nullptr && gc.level0 == level0;
+  for (int i = 0; i < 4 && same; ++i) same = gc.sig[i] == sig[i];
+  if (!same) {
+    if (gc.exec) {
+      PF_HIP_CHECK(hipGraphExecDestroy(gc.exec));
+      gc.exec = nullptr;
+    }
+    PF_HIP_CHECK(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = apply_gmg<T>(pb, H, st->gin, st->gout, st->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st->cap, &graph);
+    if (rc != PF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    PF_HIP_CHECK(ec);
+    const hipError_t ei = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) gc.exec = nullptr;
+    PF_HIP_CHECK(ei);
+    for (int i = 0; i < 4; ++i) gc.sig[i] = sig[i];
+    gc.level0 = level0;
+  }
+  hipLaunchKernelGGL(k_copy2, dim3(blocks(n)), dim3(kT), 0, s, reinterpret_cast<const double2*>(r),
+                     reinterpret_cast<double2*>(st->gin), n);
+  PF_HIP_CHECK(hipGetLastError());
+  PF_HIP_CHECK(hipGraphLaunch(gc.exec, s));
+  hipLaunchKernelGGL(k_copy2, dim3(blocks(n)), dim3(kT), 0, s,
+                     reinterpret_cast<const double2*>(st->gout), reinterpret_cast<double2*>(z), n);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
 }  // namespace
 
 int pc_alloc(pf_problem* pb) {
   PcState* st = new PcState();
   pb->pc = st;
+  // PF_GMG_GRAPH=0 keeps every V-cycle on eager launches (read at creation)
+  const char* e = std::getenv("PF_GMG_GRAPH");
+  if (e && e[0] == '0' && e[1] == '\0') st->graph_enabled = false;
   if (hipMalloc(&st->coef0, (size_t)pb->geo.n_elems * sizeof(double)) != hipSuccess) return PF_ERR_OOM;
   return PF_OK;
 }
@@ -1389,6 +1471,11 @@ hipError_t pc_free(pf_problem* pb) {
   auto keep = [&](hipError_t e) {
     if (first == hipSuccess) first = e;
   };
+  for (GraphCache* gc : {&st->g32, &st->g64})
+    if (gc->exec) keep(hipGraphExecDestroy(gc->exec));
+  if (st->cap) keep(hipStreamDestroy(st->cap));
+  if (st->gin) keep(hipFree(st->gin));
+  if (st->gout) keep(hipFree(st->gout));
   keep(hier_free(st->h32));
   keep(hier_free(st->h64));
   if (st->coef0) keep(hipFree(st->coef0));
@@ -1449,6 +1536,11 @@ int pc_apply(pf_problem* pb, const double* r, double* z, hipStream_t s) {
       return PF_OK;
     }
     default:
+      if (st->graph_enabled && pb->n_dof <= kGraphMaxDof) {
+        if (pb->pc_precision == PF_FP32)
+          return apply_gmg_graph<float>(pb, st, st->h32, st->g32, r, z, s);
+        return apply_gmg_graph<double>(pb, st, st->h64, st->g64, r, z, s);
+      }
       if (pb->pc_precision == PF_FP32) return apply_gmg<float>(pb, st->h32, r, z, s);
       return apply_gmg<double>(pb, st->h64, r, z, s);
   }
