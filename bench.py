@@ -142,12 +142,16 @@ def vcycle_bytes(dim, n, s):
     coefficients and write the iterate (6s); the last post step writes the
     iterate instead of the FP64 result (9s).  Total 37.5s.  Coarsest grid:
     coefficients, right-hand side, iterate (5s).  Levels halve while every side
-    is even and longer than 4 elements, as the hierarchy does."""
+    is even and longer than 4 elements, as the hierarchy does.  A mesh that does
+    not coarsen converts the FP64 right-hand side (16 + 2s), takes the coarse
+    solve (5s) and writes the FP64 result (2s + 16): 32 + 9s."""
     sizes = [n]
     while n % 2 == 0 and n > 4:
         n //= 2
         sizes.append(n)
     nodes = [(m + 1) ** dim for m in sizes]
+    if len(nodes) == 1:
+        return (32 + 9 * s) * nodes[0]
     total = (32 + 35.5 * s) * nodes[0]
     total += sum(37.5 * s * k for k in nodes[1:-1])
     total += 5 * s * nodes[-1]
