@@ -28,6 +28,27 @@ struct Tiles {
   int ntx, nty, ntz;
 };
 
+// Residual and FD product: node planes go from HBM straight into LDS
+// (global_load_lds_dwordx4, one double2 per lane, no registers) two planes
+// ahead through a ring of three plane slots.  PF_FUSED_DMA=0 at build time
+// keeps the register-staged loads instead.
+#ifndef PF_FUSED_DMA
+#define PF_FUSED_DMA 1
+#endif
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// One double2 per active lane from src into the LDS slot of the lane's node:
+// the instruction writes lane i of the wave at base + 16 i, so the destination
+// is the wave's first node (n rounded down to a multiple of 64).
+__device__ __forceinline__ void dma16(const double2* src, double2* lds_row, int n) {
+  __builtin_amdgcn_global_load_lds((glb_void_t*)src, (lds_void_t*)(lds_row + (n & ~63)), 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(0): this wave's outstanding memory operations, the plane
+// copies into LDS included, have completed.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 template <int MODE>
 struct ModeInfo {
   static constexpr bool kHasV = MODE != MODE_RES;
@@ -48,11 +69,17 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
              double* __restrict__ side, double* __restrict__ vjp_part, double* __restrict__ coef) {
   using MI = ModeInfo<MODE>;
   constexpr int NO = MI::NO;
-  __shared__ double2 su[2][PN];
-  __shared__ double2 sp[2][PN];
-  __shared__ double2 sv[MI::kHasV && MODE != MODE_FD ? 2 : 1][MI::kHasV && MODE != MODE_FD ? PN : 1];
+  // plane copies straight into LDS (residual, FD product): three slots
+  constexpr bool kDma = PF_FUSED_DMA && (MODE == MODE_RES || MODE == MODE_FD);
+  constexpr int NS = kDma ? 3 : 2;
+  // FD through the copies: raw U and V staged, U + eps V formed at the corner reads
+  constexpr bool kRawV = kDma && MODE == MODE_FD;
+  __shared__ double2 su[NS][PN];
+  __shared__ double2 sp[NS][PN];
+  __shared__ double2 sv[(MI::kHasV && MODE != MODE_FD) || kRawV ? NS : 1]
+                       [(MI::kHasV && MODE != MODE_FD) || kRawV ? PN : 1];
   // FD product: F0 of the staged planes, so that the node writes need no load
-  __shared__ double2 sf[MODE == MODE_FD ? 2 : 1][MODE == MODE_FD ? PN : 1];
+  __shared__ double2 sf[MODE == MODE_FD ? NS : 1][MODE == MODE_FD ? PN : 1];
   __shared__ double cb[NO][4][kThreads];
 
   const int tid = threadIdx.x;
@@ -92,6 +119,23 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
         }
         su[slot][n] = u;
         sp[slot][n] = Up[g];
+      }
+    }
+  };
+
+  // Plane z into ring slot `slot` by direct copies into LDS (kDma modes); the
+  // copies complete by the wave's next wait_vm().
+  auto dma_plane = [&](int slot, int z) {
+    for (int n = tid; n < PN; n += kThreads) {
+      const int lx = n % PX, ly = n / PX;
+      if (lx <= lxmax && ly <= lymax) {
+        const long long g = gnode(G, x0 + lx, y0 + ly, z);
+        dma16(U + g, &su[slot][0], n);
+        dma16(Up + g, &sp[slot][0], n);
+        if (kRawV) {
+          dma16(V + g, &sv[slot][0], n);
+          dma16(F0 + g, &sf[slot][0], n);
+        }
       }
     }
   };
@@ -164,7 +208,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     }
     const long long g = gnode(G, x0 + lx, y0 + ly, z0 + lz);
     if (MODE == MODE_FD) {
-      const double2 f0 = sf[lz & 1][n];
+      const double2 f0 = sf[kDma ? lz % 3 : lz & 1][n];
       const double ie = eps == 0.0 ? 0.0 : 1.0 / eps;
       out0[g] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
     } else {
@@ -196,26 +240,40 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   };
 
   double ge = 0.0, gl = 0.0;
-  load_plane(0, z0);
-  if (kPrefetch) {
-    load_plane(1, z0 + 1);
+  if (kDma) {
+    dma_plane(0, z0);
+    dma_plane(1, z0 + 1);
+    wait_vm();
     __syncthreads();
+  } else {
+    load_plane(0, z0);
+    if (kPrefetch) {
+      load_plane(1, z0 + 1);
+      __syncthreads();
+    }
   }
   for (int kz = 0; kz < kzmax; ++kz) {
-    const int bot = kz & 1, top = bot ^ 1;
+    // ring slots: plane kz in kz % 3 (copies) or kz & 1
+    const int bot = kDma ? kz % 3 : kz & 1;
+    const int top = kDma ? (kz + 1) % 3 : bot ^ 1;
     const bool more = kPrefetch && kz + 2 <= kzmax;  // plane z0 + kz + 2 exists in this chunk
-    if (!kPrefetch) {
+    if (!kDma && !kPrefetch) {
       load_plane(top, z0 + kz + 1);
       __syncthreads();
     }
     double out[NO][8];
+    double u0[8], u1[8], p0[8], p1[8], v0[8], v1[8];
     if (has_elem) {
-      double u0[8], u1[8], p0[8], p1[8], v0[8], v1[8];
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         const int slot = (a & 4) ? top : bot;
         const int n = (ei + (a & 1)) + PX * (ej + ((a >> 1) & 1));
-        const double2 u = su[slot][n];
+        double2 u = su[slot][n];
+        if (kRawV) {
+          const double2 v = sv[slot][n];
+          u.x = fma(eps, v.x, u.x);
+          u.y = fma(eps, v.y, u.y);
+        }
         const double2 up = sp[slot][n];
         u0[a] = u.x;
         u1[a] = u.y;
@@ -229,6 +287,12 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
           v0[a] = v1[a] = 0.0;
         }
       }
+    }
+    // the next-but-one plane is copied once the corner values are in registers
+    // (the compiler orders LDS reads of the ring after copies into it): slot
+    // (kz + 2) % 3 last held plane kz - 1, which no lane reads any more
+    if (kDma && kz + 2 <= kzmax) dma_plane((kz + 2) % 3, z0 + kz + 2);
+    if (has_elem) {
       double eg = 0.0, lg = 0.0;
       Element<3, MODE>::run(G, u0, u1, p0, p1, v0, v1, out, eg, lg);
       if (MODE == MODE_RES) {
@@ -277,6 +341,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
     __syncthreads();
     gather(nA, carryA);
     if (ownB) gather(nB, carryB);
+    // the plane copied at the top of this iteration is read in the next one
+    if (kDma) wait_vm();
     __syncthreads();
   }
   emit(nA, kzmax, carryA);
