@@ -35,6 +35,10 @@ struct Tiles {
 #ifndef PF_FUSED_DMA
 #define PF_FUSED_DMA 1
 #endif
+// the same copies for the tangent and adjoint kernels (else register prefetch)
+#ifndef PF_FUSED_DMA_ALL
+#define PF_FUSED_DMA_ALL 1
+#endif
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
 
@@ -70,7 +74,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   using MI = ModeInfo<MODE>;
   constexpr int NO = MI::NO;
   // plane copies straight into LDS (residual, FD product): three slots
-  constexpr bool kDma = PF_FUSED_DMA && (MODE == MODE_RES || MODE == MODE_FD);
+  constexpr bool kDma = PF_FUSED_DMA && (PF_FUSED_DMA_ALL || MODE == MODE_RES || MODE == MODE_FD);
   constexpr int NS = kDma ? 3 : 2;
   // FD through the copies: raw U and V staged, U + eps V formed at the corner reads
   constexpr bool kRawV = kDma && MODE == MODE_FD;
@@ -135,6 +139,8 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
         if (kRawV) {
           dma16(V + g, &sv[slot][0], n);
           dma16(F0 + g, &sf[slot][0], n);
+        } else if (MI::kHasV && MODE != MODE_FD) {
+          dma16(V + g, &sv[slot][0], n);
         }
       }
     }
@@ -147,7 +153,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   // node-sum phase.  The residual and FD product run two workgroups per
   // compute unit, which cover each other's loads, and have no registers to
   // spare for it.
-  constexpr bool kPrefetch = !(MODE == MODE_RES || MODE == MODE_FD);
+  constexpr bool kPrefetch = !kDma && !(MODE == MODE_RES || MODE == MODE_FD);
   static_assert(!(kPrefetch && MODE == MODE_FD), "the prefetch path does not stage F0");
   // Node tid of the plane goes through registers; the few nodes beyond the
   // first kThreads are read when stored.
