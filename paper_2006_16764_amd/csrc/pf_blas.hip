@@ -47,15 +47,25 @@ __global__ void __launch_bounds__(kRedThreads)
   const int j0 = c * kChunk;
   const long long n2 = n / 2;
   const double2* w2 = reinterpret_cast<const double2*>(w);
-  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
-       i += (long long)nb * kRedThreads) {
-    const double2 wi = w2[i];
+  if (k == 1 && V == w) {
+    // a squared norm: one load per entry instead of two of the same address
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
+         i += (long long)nb * kRedThreads) {
+      const double2 wi = w2[i];
+      acc[0] = fma(wi.x, wi.x, acc[0]);
+      acc[0] = fma(wi.y, wi.y, acc[0]);
+    }
+  } else {
+    for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
+         i += (long long)nb * kRedThreads) {
+      const double2 wi = w2[i];
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      if (j0 + j < k) {
-        const double2 vi = reinterpret_cast<const double2*>(V + (long long)(j0 + j) * ld)[i];
-        acc[j] = fma(vi.x, wi.x, acc[j]);
-        acc[j] = fma(vi.y, wi.y, acc[j]);
+      for (int j = 0; j < kChunk; ++j) {
+        if (j0 + j < k) {
+          const double2 vi = reinterpret_cast<const double2*>(V + (long long)(j0 + j) * ld)[i];
+          acc[j] = fma(vi.x, wi.x, acc[j]);
+          acc[j] = fma(vi.y, wi.y, acc[j]);
+        }
       }
     }
   }
