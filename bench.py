@@ -101,7 +101,7 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
     "bytes": 1428670704,
-    "sources_sha256": "89ee4f9c5a6519af5c9e2abaf5e8731dc9983136694418ebc265fe6779c6c4f3",
+    "sources_sha256": "0000b48f48dcef6d767eeba5a8c2fccea4497a9ed50329b3345a2bef4dde6226",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h")
 
