@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pf_internal.h"
@@ -538,7 +539,7 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
       return std::isfinite(ft) ? PF_ERR_LINESEARCH : PF_ERR_NONFINITE;
     }
     PF_HIP_CHECK(hipMemcpyAsync(U, Ut, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    PF_HIP_CHECK(hipMemcpyAsync(F, Ft, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    std::swap(F, Ft);  // the accepted trial residual becomes F (both are work vectors)
     // forcing term for the next linear solve
     const double ratio = ft / f;
     double en = o.gamma * std::pow(ratio, o.omega);
