@@ -181,7 +181,10 @@ int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v
  *   gU     = (dF/dU)^T w         (may be NULL)
  *   gUprev = (dF/dUprev)^T w     (may be NULL)
  *   gparams[0] = w . dF/d eps4, gparams[1] = w . dF/d lambda  (device, 2
- *   doubles; may be NULL).  Reductions are deterministic. */
+ *   doubles; may be NULL).  Reductions are deterministic.  With gU NULL a 3-D
+ *   call runs a lighter kernel that forms gUprev and gparams only (no
+ *   Hessian-vector product of the anisotropic flux); its results equal those
+ *   of a call with gU to rounding. */
 int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w,
            double* gU, double* gUprev, double* gparams, void* stream);
 

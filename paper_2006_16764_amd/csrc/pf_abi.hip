@@ -892,8 +892,9 @@ int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w
   if (gU) PF_TRY(check_vec(gU, "gU"));
   if (gUprev) PF_TRY(check_vec(gUprev, "gUprev"));
   hipStream_t s = S(stream);
-  PF_TRY(launch_residual_family(pb, MODE_VJP, U, Uprev, w, nullptr, nullptr, gU, gUprev,
-                                pb->vjp_partials, s));
+  // without gU the lean kernel (previous state and parameters only) serves
+  PF_TRY(launch_residual_family(pb, gU ? MODE_VJP : MODE_VJPP, U, Uprev, w, nullptr, nullptr, gU,
+                                gUprev, pb->vjp_partials, s));
   if (gparams) PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gparams, 1.0, s));
   return PF_OK;
 }
@@ -1082,7 +1083,7 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   if (rc != PF_OK) return rc;
   double* gP = pb->tmp_vec[4];
   double* gp_local = pb->red_out + kSlotParams;
-  PF_TRY(launch_residual_family(pb, MODE_VJP, U, Uprev, lam, nullptr, nullptr, nullptr, gP,
+  PF_TRY(launch_residual_family(pb, MODE_VJPP, U, Uprev, lam, nullptr, nullptr, nullptr, gP,
                                 pb->vjp_partials, s));
   PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gp_local, 1.0, s));
   PF_TRY(blas_sub_scalars(gparams, gp_local, 2, s));

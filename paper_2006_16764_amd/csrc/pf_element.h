@@ -120,7 +120,7 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // x weights only and scaled once per row.
 template <int NG, int NV, int NS, int NP, class Phys>
 __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
-                                     const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS][8],
+                                     const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS > 0 ? NS : 1][8],
                                      double (&op)[NP > 0 ? NP : 1][8], Phys& phys) {
   const double ihx = G.ih[0], ihy = G.ih[1], ihz = G.ih[2];
 #pragma unroll 1
@@ -141,7 +141,7 @@ __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
     for (int f = 0; f < NV; ++f)
 #pragma unroll
       for (int a = 0; a < 4; ++a) pv[f][a] = fma(bz1, nv[f][a + 4] - nv[f][a], nv[f][a]);
-    double S[NS][4], Zc[NS][4], P[NP > 0 ? NP : 1][4];
+    double S[NS > 0 ? NS : 1][4], Zc[NS > 0 ? NS : 1][4], P[NP > 0 ? NP : 1][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -178,7 +178,7 @@ __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
       }
 #pragma unroll
       for (int f = 0; f < NV; ++f) dqw[f] = qw[f][1] - qw[f][0];
-      double rs[NS][2], rx[NS], ry[NS][2], rz[NS][2], rp[NP > 0 ? NP : 1][2];
+      double rs[NS > 0 ? NS : 1][2], rx[NS > 0 ? NS : 1], ry[NS > 0 ? NS : 1][2], rz[NS > 0 ? NS : 1][2], rp[NP > 0 ? NP : 1][2];
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
         rx[o] = 0.0;
@@ -198,7 +198,7 @@ __device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
         }
 #pragma unroll
         for (int f = 0; f < NV; ++f) vv[f] = fma(bx1, dqw[f], qw[f][0]);
-        double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
+        double s[NS > 0 ? NS : 1], fl[NS > 0 ? NS : 1][3], p[NP > 0 ? NP : 1];
         phys(gv, gg, vv, s, fl, p);
         const double wq = Q1::w(gx), w0 = Q1::c0(gx), w1 = Q1::c1(gx);
         phys.weight(wq);
@@ -273,7 +273,7 @@ PF_UNROLL(PF_GY_UNROLL)
 // ----------------------------------------------------------------- Gauss-rule part, 2-D
 template <int NG, int NV, int NS, int NP, class Phys>
 __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
-                                     const double (&nv)[NV > 0 ? NV : 1][4], double (&os)[NS][4],
+                                     const double (&nv)[NV > 0 ? NV : 1][4], double (&os)[NS > 0 ? NS : 1][4],
                                      double (&op)[NP > 0 ? NP : 1][4], Phys& phys) {
   const double ihx = G.ih[0], ihy = G.ih[1];
 #pragma unroll
@@ -302,7 +302,7 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
     }
 #pragma unroll
     for (int f = 0; f < NV; ++f) dqw[f] = qw[f][1] - qw[f][0];
-    double rs[NS][2], rx[NS], ry[NS][2], rp[NP > 0 ? NP : 1][2];
+    double rs[NS > 0 ? NS : 1][2], rx[NS > 0 ? NS : 1], ry[NS > 0 ? NS : 1][2], rp[NP > 0 ? NP : 1][2];
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
       rx[o] = 0.0;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
       }
 #pragma unroll
       for (int f = 0; f < NV; ++f) vv[f] = fma(bx1, dqw[f], qw[f][0]);
-      double s[NS], fl[NS][3], p[NP > 0 ? NP : 1];
+      double s[NS > 0 ? NS : 1], fl[NS > 0 ? NS : 1][3], p[NP > 0 ? NP : 1];
       phys(gv, gg, vv, s, fl, p);
       const double wq = Q1::w(gx), w0 = Q1::c0(gx), w1 = Q1::c1(gx);
       phys.weight(wq);
@@ -579,6 +579,53 @@ struct PhysVjpU {
   }
 };
 
+// Adjoint of F1 with respect to the previous state and the parameters only:
+// gradient fields {phi, w1}; value fields {u, phi - phi^n}; one value-only
+// output, gUprev_phi (time term); the parameter sums as PhysVjp.  No
+// (dF1/dU)^T w1 part, so no Hessian-vector product.
+template <int DIM>
+struct PhysVjpPrev {
+  static constexpr int kGxUnroll = 3;
+  static constexpr int kGyUnroll = PF_GY_UNROLL;
+  const Geo& G;
+  double ge, gl;
+  double ger, glr;
+  double pe, pl;
+  __device__ PhysVjpPrev(const Geo& g)
+      : G(g), ge(0.0), gl(0.0), ger(0.0), glr(0.0), pe(0.0), pl(0.0) {}
+  __device__ __forceinline__ void weight(double wx) {
+    ger = fma(wx, pe, ger);
+    glr = fma(wx, pl, glr);
+  }
+  __device__ __forceinline__ void row(double wrow) {
+    ge = fma(wrow, ger, ge);
+    gl = fma(wrow, glr, gl);
+    ger = glr = 0.0;
+  }
+  __device__ __forceinline__ void operator()(const double* gv, const double (*gg)[3],
+                                             const double* vv, double*, double (*)[3],
+                                             double* p) {
+    const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
+    Aniso<DIM> A;
+    A.flux(gg[0], G);
+    const double om = 1.0 - phi * phi;
+    const double m = 2.0 * A.a * dphi * G.idtm * w1;
+    p[0] = -w1 * A.a2 * G.idtm;
+    const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
+    double Je_w = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const double gk = gg[0][k];
+      const double dae = 16.0 * A.iQ2 * gk * (A.g2[k] - A.SQ);
+      const double dak = G.eps4 * dae;
+      const double Je = 2.0 * A.a * ae * gk + ae * A.q * dak + A.a * A.q * dae;
+      Je_w += Je * gg[1][k];
+    }
+    pe = m * ae + Je_w;
+    pl = w1 * om * om * u;
+  }
+};
+
 // ----------------------------------------------------------------- whole-element routine
 // Corner values (a = 0 .. 2^DIM - 1): u0/u1 = (phi, u) of the state, p0/p1 =
 // (phi^n, u^n), v0/v1 = direction (JVP) or cotangent (VJP) parts.  For the FD
@@ -592,7 +639,7 @@ struct Element {
 
   template <int NG, int NV, int NS, int NP, class Phys>
   __device__ __forceinline__ static void quad(const Geo& G, const double (&ng)[NG][NA],
-                                              const double (&nv)[NV][NA], double (&os)[NS][NA],
+                                              const double (&nv)[NV][NA], double (&os)[NS > 0 ? NS : 1][NA],
                                               double (&op)[NP > 0 ? NP : 1][NA], Phys& ph) {
     if constexpr (DIM == 3) quad3<NG, NV, NS, NP>(G, ng, nv, os, op, ph);
     else quad2<NG, NV, NS, NP>(G, ng, nv, os, op, ph);
@@ -684,6 +731,31 @@ struct Element {
 #pragma unroll
       for (int a = 0; a < NA; ++a) zero[a] = 0.0;
       lin(G, y, -G.hth, zero, 0.0, out[0]);
+    } else if constexpr (MODE == MODE_VJPP) {
+      // previous-state part of the adjoint: gUprev_phi = theta (time term) +
+      // theta M w2/(2dt), gUprev_u = -M w2/dt; the parameter sums
+      double zero[NA], mw[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) zero[a] = mw[a] = 0.0;
+      lin(G, v1, 1.0, zero, 0.0, mw);
+      double ngv[2][NA], nvv[2][NA], os[1][NA], op[1][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        ngv[0][a] = u0[a];
+        ngv[1][a] = v0[a];
+        nvv[0][a] = u1[a];
+        nvv[1][a] = dphi[a];
+        op[0][a] = 0.0;
+      }
+      PhysVjpPrev<DIM> ph(G);
+      quad<2, 2, 0, 1>(G, ngv, nvv, os, op, ph);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        out[0][a] = G.theta * op[0][a] + G.hth * G.idt * mw[a];
+        out[1][a] = -G.idt * mw[a];
+      }
+      ge = G.theta * ph.ge;
+      gl = G.theta * ph.gl;
     } else {
       // F2 part of the adjoint (M, K symmetric): gU_phi -= theta M w2/(2dt),
       // gU_u += M w2/dt + theta D K w2, gUprev_phi += theta M w2/(2dt),

@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
         u1[a] = u.y;
         p0[a] = up.x;
         p1[a] = up.y;
-        if (MODE == MODE_JVP || MODE == MODE_VJP || MODE == MODE_VJPU) {
+        if (MODE == MODE_JVP || MODE == MODE_VJP || MODE == MODE_VJPU || MODE == MODE_VJPP) {
           const double2 v = sv[slot][n];
           v0[a] = v.x;
           v1[a] = v.y;
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
   emit(nA, kzmax, carryA);
   if (ownB) emit(nB, kzmax, carryB);
 
-  if (MODE == MODE_VJP) {
+  if (MODE == MODE_VJP || MODE == MODE_VJPP) {
     // fixed-order block reduction of the parameter sums (cb reused as scratch)
     double* red = &cb[0][0][0];
     red[tid] = ge;
@@ -494,6 +494,8 @@ int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev
       return launch_mode<MODE_JVP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     case MODE_VJPU:
       return launch_mode<MODE_VJPU>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+    case MODE_VJPP:
+      return launch_mode<MODE_VJPP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     default:
       return launch_mode<MODE_VJP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
   }

@@ -90,7 +90,9 @@ struct FgConst {
 
 // Element-loop modes of the residual kernel family.
 // MODE_VJPU: (dF/dU)^T w only (the operator of the transposed Krylov solve).
-enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4 };
+// MODE_VJPP: the adjoint's previous-state output (dF/dUprev)^T w and the two
+// parameter sums only (no (dF/dU)^T w).
+enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4, MODE_VJPP = 5 };
 
 // 3-D single-pass kernels (pf_fused3.hip).
 long long fused3_side_len(const Geo& G);

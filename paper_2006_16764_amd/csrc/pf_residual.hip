@@ -221,6 +221,13 @@ int launch_residual_family(pf_problem* pb, int mode, const double* U, const doub
                            double* coef) {
   if (pb->model == 1) return launch_alloy(pb, mode, U, Uprev, v, F0, eps_dev, out0, coef, s);
   if (pb->model == 2) return launch_fg(pb, mode, U, Uprev, v, F0, eps_dev, out0, coef, s);
+  if (mode == MODE_VJPP) {
+    // out1 receives (dF/dUprev)^T w; the fused 3-D kernel writes its one
+    // output through out0, the 2-D path runs the full adjoint without gU
+    if (pb->geo.dim == 3)
+      return launch_fused3(pb, MODE_VJPP, U, Uprev, v, F0, eps_dev, out1, nullptr, vjp_part, coef, s);
+    return launch_dim<2>(pb, MODE_VJP, U, Uprev, v, F0, eps_dev, nullptr, out1, vjp_part, coef, s);
+  }
   if (pb->geo.dim == 3)
     return launch_fused3(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
   return launch_dim<2>(pb, mode, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);

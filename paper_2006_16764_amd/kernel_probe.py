@@ -24,7 +24,9 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="seeds3d_256")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--only", default="", help="comma list: copy,residual,fd,jvp,vjp,pc32,pc64")
+    ap.add_argument("--only", default="",
+                    help="comma list: copy,residual,fd,jvp,vjp,pc32,pc64; vjpp (the VJP "
+                         "without gU) runs only when named here")
     a = ap.parse_args(argv)
     only = set(a.only.split(",")) if a.only else None
     w = inputs.workload(a.workload)
@@ -57,9 +59,10 @@ def main(argv=None) -> int:
         ("fd", lambda: pb.pf_jvp(U, U0, v, out, mode=binding.PF_JV_FD, F0=F)),
         ("jvp", lambda: pb.pf_jvp(U, U0, v, out, mode=binding.PF_JV_ANALYTIC)),
         ("vjp", lambda: pb.pf_vjp(U, U0, v, out, out2, gp)),
+        ("vjpp", lambda: pb.pf_vjp(U, U0, v, None, out2, gp)),
     ]
     for name, fn in calls:
-        if want(name):
+        if want(name) and (name != "vjpp" or only is not None):
             for _ in range(a.reps):
                 fn()
             torch.cuda.synchronize()

@@ -127,6 +127,33 @@ def test_vjp_parity(case):
     assert abs(gpn[1] - rgl) < 1e-12 * max(1.0, abs(rgl)) * 10
 
 
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+def test_vjp_without_gU_parity(case):
+    # gU omitted: the previous-state and parameter parts come from the lean
+    # kernel in 3-D and must equal the oracle and the full adjoint's
+    note(f"vjp without gU {case}")
+    mesh, p, U, Up, pb = setup_case(case, 7)
+    w = inputs.random_vector(mesh.n_nodes, 11)
+    Ud, Upd, wd = dev(U), dev(Up), dev(w)
+    gP = pb.new_vector()
+    gp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    pb.pf_vjp(Ud, Upd, wd, None, gP, gp)
+    _, rgP, rge, rgl = deriv.vjp(mesh, U, Up, w, p)
+    assert rel(host(gP), rgP) < 1e-12
+    gpn = gp.cpu().numpy()
+    assert abs(gpn[0] - rge) < 1e-12 * max(1.0, abs(rge)) * 10
+    assert abs(gpn[1] - rgl) < 1e-12 * max(1.0, abs(rgl)) * 10
+    gU2, gP2 = pb.new_vector(), pb.new_vector()
+    gp2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    pb.pf_vjp(Ud, Upd, wd, gU2, gP2, gp2)
+    assert rel(host(gP), host(gP2)) < 1e-13
+    assert np.allclose(gp.cpu().numpy(), gp2.cpu().numpy(), rtol=1e-13, atol=0.0)
+    # parameters only
+    gp3 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    pb.pf_vjp(Ud, Upd, wd, None, None, gp3)
+    assert np.array_equal(gp.cpu().numpy(), gp3.cpu().numpy())
+
+
 def test_residual_is_bitwise_deterministic():
     note("determinism")
     mesh, p, U, Up, pb = setup_case(CASES[3], 1)
