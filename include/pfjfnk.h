@@ -184,7 +184,8 @@ int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v
  *   doubles; may be NULL).  Reductions are deterministic.  With gU NULL a 3-D
  *   call runs a lighter kernel that forms gUprev and gparams only (no
  *   Hessian-vector product of the anisotropic flux); its results equal those
- *   of a call with gU to rounding. */
+ *   of a call with gU to rounding.  With gU alone (gUprev and gparams NULL)
+ *   the call runs the kernel of the transposed Krylov operator. */
 int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w,
            double* gU, double* gUprev, double* gparams, void* stream);
 

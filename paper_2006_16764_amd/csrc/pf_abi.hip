@@ -892,7 +892,11 @@ int pf_vjp(pf_problem* pb, const double* U, const double* Uprev, const double* w
   if (gU) PF_TRY(check_vec(gU, "gU"));
   if (gUprev) PF_TRY(check_vec(gUprev, "gUprev"));
   hipStream_t s = S(stream);
-  // without gU the lean kernel (previous state and parameters only) serves
+  // lean kernels where outputs are left out: gU alone is the transposed
+  // operator; without gU only the previous state and the parameters are formed
+  if (gU && !gUprev && !gparams)
+    return launch_residual_family(pb, MODE_VJPU, U, Uprev, w, nullptr, nullptr, gU, nullptr,
+                                  nullptr, s);
   PF_TRY(launch_residual_family(pb, gU ? MODE_VJP : MODE_VJPP, U, Uprev, w, nullptr, nullptr, gU,
                                 gUprev, pb->vjp_partials, s));
   if (gparams) PF_TRY(blas_reduce_partials(pb->vjp_partials, pb->n_elem_blocks, 2, gparams, 1.0, s));

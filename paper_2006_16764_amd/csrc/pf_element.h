@@ -31,6 +31,11 @@
 #ifndef PF_GY_UNROLL
 #define PF_GY_UNROLL 3
 #endif
+// The x-point loop of the tangent and adjoint functors: 3 unrolls it, 1 keeps
+// it rolled.
+#ifndef PF_TAN_GX_UNROLL
+#define PF_TAN_GX_UNROLL 3
+#endif
 #define PF_PRAGMA(x) _Pragma(#x)
 #define PF_UNROLL(n) PF_PRAGMA(unroll n)
 
@@ -466,7 +471,7 @@ struct PhysResidual {
 // {u, phi - phi^n, v_u}.
 template <int DIM>
 struct PhysJvp {
-  static constexpr int kGxUnroll = 3;
+  static constexpr int kGxUnroll = PF_TAN_GX_UNROLL;
   static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   __device__ PhysJvp(const Geo& g) : G(g) {}
@@ -497,7 +502,7 @@ struct PhysJvp {
 // w1 . dF1/d lambda (F2 does not depend on the parameters).
 template <int DIM>
 struct PhysVjp {
-  static constexpr int kGxUnroll = 3;
+  static constexpr int kGxUnroll = PF_TAN_GX_UNROLL;
   static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   double ge, gl;    // element accumulators
@@ -553,7 +558,7 @@ struct PhysVjp {
 // fields {u, phi - phi^n}; outputs gU_phi (value + flux) and value-only gU_u.
 template <int DIM>
 struct PhysVjpU {
-  static constexpr int kGxUnroll = 3;
+  static constexpr int kGxUnroll = PF_TAN_GX_UNROLL;
   static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   __device__ PhysVjpU(const Geo& g) : G(g) {}
@@ -585,7 +590,7 @@ struct PhysVjpU {
 // (dF1/dU)^T w1 part, so no Hessian-vector product.
 template <int DIM>
 struct PhysVjpPrev {
-  static constexpr int kGxUnroll = 3;
+  static constexpr int kGxUnroll = PF_TAN_GX_UNROLL;
   static constexpr int kGyUnroll = PF_GY_UNROLL;
   const Geo& G;
   double ge, gl;

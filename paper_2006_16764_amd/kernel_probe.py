@@ -26,7 +26,7 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--only", default="",
                     help="comma list: copy,residual,fd,jvp,vjp,pc32,pc64; vjpp (the VJP "
-                         "without gU) runs only when named here")
+                         "without gU) and vjpu (gU alone) run only when named here")
     a = ap.parse_args(argv)
     only = set(a.only.split(",")) if a.only else None
     w = inputs.workload(a.workload)
@@ -60,9 +60,10 @@ def main(argv=None) -> int:
         ("jvp", lambda: pb.pf_jvp(U, U0, v, out, mode=binding.PF_JV_ANALYTIC)),
         ("vjp", lambda: pb.pf_vjp(U, U0, v, out, out2, gp)),
         ("vjpp", lambda: pb.pf_vjp(U, U0, v, None, out2, gp)),
+        ("vjpu", lambda: pb.pf_vjp(U, U0, v, out, None, None)),
     ]
     for name, fn in calls:
-        if want(name) and (name != "vjpp" or only is not None):
+        if want(name) and (name not in ("vjpp", "vjpu") or only is not None):
             for _ in range(a.reps):
                 fn()
             torch.cuda.synchronize()

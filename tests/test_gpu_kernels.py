@@ -128,17 +128,17 @@ def test_vjp_parity(case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
-def test_vjp_without_gU_parity(case):
-    # gU omitted: the previous-state and parameter parts come from the lean
-    # kernel in 3-D and must equal the oracle and the full adjoint's
-    note(f"vjp without gU {case}")
+def test_vjp_partial_outputs_parity(case):
+    # outputs left out: the lean kernels (previous state and parameters in
+    # 3-D; gU alone) must equal the oracle and the full adjoint's
+    note(f"vjp partial outputs {case}")
     mesh, p, U, Up, pb = setup_case(case, 7)
     w = inputs.random_vector(mesh.n_nodes, 11)
     Ud, Upd, wd = dev(U), dev(Up), dev(w)
     gP = pb.new_vector()
     gp = torch.zeros(2, dtype=torch.float64, device="cuda")
     pb.pf_vjp(Ud, Upd, wd, None, gP, gp)
-    _, rgP, rge, rgl = deriv.vjp(mesh, U, Up, w, p)
+    rgU, rgP, rge, rgl = deriv.vjp(mesh, U, Up, w, p)
     assert rel(host(gP), rgP) < 1e-12
     gpn = gp.cpu().numpy()
     assert abs(gpn[0] - rge) < 1e-12 * max(1.0, abs(rge)) * 10
@@ -148,6 +148,11 @@ def test_vjp_without_gU_parity(case):
     pb.pf_vjp(Ud, Upd, wd, gU2, gP2, gp2)
     assert rel(host(gP), host(gP2)) < 1e-13
     assert np.allclose(gp.cpu().numpy(), gp2.cpu().numpy(), rtol=1e-13, atol=0.0)
+    # gU alone: the transposed Krylov operator's kernel
+    gU4 = pb.new_vector()
+    pb.pf_vjp(Ud, Upd, wd, gU4, None, None)
+    assert rel(host(gU4), rgU) < 1e-12
+    assert rel(host(gU4), host(gU2)) < 1e-13
     # parameters only
     gp3 = torch.zeros(2, dtype=torch.float64, device="cuda")
     pb.pf_vjp(Ud, Upd, wd, None, None, gp3)
