@@ -101,7 +101,7 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
     "bytes": 1428670704,
-    "sources_sha256": "5dd1f6a8a1073bf2e233ade9a1e7026e84a9ea09efaf691ff88232274cb8bdd5",
+    "sources_sha256": "2610a67f6c5d49635c573b57715e545004b50befa380b6db47b975fbbe973d97",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h")
 
