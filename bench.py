@@ -101,7 +101,7 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
     "bytes": 1428670704,
-    "sources_sha256": "2610a67f6c5d49635c573b57715e545004b50befa380b6db47b975fbbe973d97",
+    "sources_sha256": "de54692fbfb1654b01f9bef68465df7a6809097c16d09ac927ea65d2e24fd03a",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h")
 

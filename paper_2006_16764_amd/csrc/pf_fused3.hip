@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kThreads, (MODE == MODE_RES || MODE == MODE_FD
 
   const long long tile_base = (long long)tile * (KZ + 1) * PN;
   // Write the sum of node n (local) of plane lz: final value or side-buffer
-  // partial.  Plane lz is staged in slot lz & 1.
+  // partial.  Plane lz is staged in slot lz % 3 (plane copies) or lz & 1.
   auto emit = [&](int n, int lz, const double* acc) {
     const int lx = n % PX, ly = n / PX;
     if (lx > lxmax || ly > lymax) return;
