@@ -239,6 +239,9 @@ def main():
     t_fd = time_call(lambda: pb.pf_jvp(U, Uprev, vdir, Jv, mode=binding.PF_JV_FD, F0=F), reps)
     t_jv = time_call(lambda: pb.pf_jvp(U, Uprev, vdir, Jv, mode=binding.PF_JV_ANALYTIC), reps)
     t_vjp = time_call(lambda: pb.pf_vjp(U, Uprev, vdir, gU, gP, gp), reps)
+    # the adjoint solve's two lean products: gU alone, and gUprev with the parameters
+    t_vjp_u = time_call(lambda: pb.pf_vjp(U, Uprev, vdir, gU, None, None), reps)
+    t_vjp_prev = time_call(lambda: pb.pf_vjp(U, Uprev, vdir, None, gP, gp), reps)
     t_setup32 = time_call(lambda: pb.pf_precond_setup(U, binding.PF_PC_GMG, binding.PF_FP32), reps)
     t_pc32 = time_call(lambda: pb.pf_precond_apply(vdir, Jv), reps)
     pb.pf_precond_setup(U, binding.PF_PC_GMG, binding.PF_FP64)
@@ -331,10 +334,12 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": residual_traffic(w.name),
                      "hbm_gbs_algorithmic": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / 8000.0, 4)},
         "kernels_ms": {"residual": round(t_res, 4), "fd_jv": round(t_fd, 4), "analytic_jv": round(t_jv, 4),
-                       "vjp": round(t_vjp, 4), "pc_setup_fp32": round(t_setup32, 4),
+                       "vjp": round(t_vjp, 4), "vjp_gU_only": round(t_vjp_u, 4),
+                       "vjp_prev_and_params": round(t_vjp_prev, 4), "pc_setup_fp32": round(t_setup32, 4),
                        "vcycle_fp32": round(t_pc32, 4), "vcycle_fp64": round(t_pc64, 4)},
         "kernels_mdofs": {k: round(n / (v * 1e-3) / 1e6, 1) for k, v in
-                          (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv), ("vjp", t_vjp))},
+                          (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv), ("vjp", t_vjp),
+                           ("vjp_gU_only", t_vjp_u), ("vjp_prev_and_params", t_vjp_prev))},
         "kernels_fp64": ({k: {"tflops": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12, 2),
                               "frac": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12 / peak, 3)}
                           for k, v in (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv),
