@@ -30,7 +30,14 @@ COARSE_DEGREE on [lmin, 1.1 lmax].  The V-cycle takes its steps in this order:
   pre-smooth from zero, residual, restrict, recurse, prolong and add,
   post-smooth from the corrected iterate.
 
-Pins: V-cycle contraction and symmetry tests; repeated V-cycles converge to the
+Pins: the u block equals the u-u block of the complex-step Jacobian for any
+state, theta, dt and D; with eps4 = lambda = 0 the phi block equals the phi-phi
+Jacobian block plus the reaction-weighted mass matrix, and at a constant state
+it equals the textbook Kronecker form with c = (1 - 3 eps4)^2; the cell
+coefficient equals the mobility the residual's time term integrates (element
+sums of dF/dU^n) and the closed forms of a along <100>, <110>, <111>; the
+coarsening of a separable coefficient is the tensor product of 1-D pair means;
+V-cycle contraction and symmetry tests; repeated V-cycles converge to the
 direct solve; the smoother equals the closed-form Chebyshev error polynomial of
 its interval and the whole cycle equals its closed-form operator
 (I - E) A^-1, E = S (I - P B_c P^T A) S, built from dense matrices.  The
