@@ -117,8 +117,9 @@ typedef struct {
 } pf_solver_opts;
 
 /* Statistics of one pf_newton_step / pf_linear_solve / pf_adjoint_step call.
- * Times are host wall-clock milliseconds per phase (stream synchronised at
- * phase ends only when the call is [sync] anyway). */
+ * t_total_ms is the host wall-clock time of the call's own work: a [sync]
+ * call first drains the stream of what the caller queued before it, then
+ * starts its clock. */
 typedef struct {
   int status;
   int newton_its;
@@ -155,10 +156,14 @@ int pf_set_params(pf_problem* pb, const pf_params* params);
 /* Number of nodes and of unknowns (2 * nodes) of the handle's mesh. */
 long long pf_num_nodes(const pf_problem* pb);
 
-/* [async] F = F(U; Uprev), the part of the step residual above that depends
- * on U (Sec. 2.1.2, Eqs. dpf, dtemp; the whole residual when theta = 1).
- * U, Uprev, F: device, 2*n_nodes doubles.  F must not alias U or Uprev. */
-int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F, void* stream);
+/* [async] F = F(U; Uprev) - rhs, the part of the step residual above that
+ * depends on U (Sec. 2.1.2, Eqs. dpf, dtemp; the whole residual when
+ * theta = 1), less an optional load vector rhs (e.g. the volume and boundary
+ * integrals of a manufactured solution; NULL for none).  The subtraction is one
+ * rounding of the exact difference.  U, Uprev, rhs, F: device, 2*n_nodes
+ * doubles.  F must not alias U, Uprev or rhs. */
+int pf_residual(pf_problem* pb, const double* U, const double* Uprev, const double* rhs, double* F,
+                void* stream);
 
 /* [async] E = E(Uprev, Uprev2), the part of the step residual fixed by the two
  * previous states (Eqs. dpf, dtemp and the lagged half of the rate of Eq.
@@ -260,6 +265,17 @@ int pf_evolve(pf_problem* pb, double* states, int steps, const pf_solver_opts* o
 int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const double* mu,
                     double* lam, double* mu_prev, double* gparams, const pf_solver_opts* opts,
                     pf_solver_stats* stats, void* stream);
+
+/* [sync] Adjoint solve of Sec. 2.2's Jacobian: F'(U)^T lam = rhs (E held
+ * fixed, any theta) by right-preconditioned FGMRES with the transposed
+ * residual-family kernel as operator and the preconditioner of Eq. pre
+ * (symmetric, so it serves the transposed system unchanged) set up at U with
+ * opts->pc and opts->pc_precision, to |rhs - F'(U)^T lam| <= opts->tau_r |rhs|
+ * from lam = 0.  U, Uprev, rhs, lam: device, 2*n_nodes doubles; lam must not
+ * alias the inputs.  PF_ERR_LINEAR when opts->gmres_maxit iterations do not
+ * reach the tolerance (lam holds the last iterate). */
+int pf_adjoint_solve(pf_problem* pb, const double* U, const double* Uprev, const double* rhs,
+                     double* lam, const pf_solver_opts* opts, pf_solver_stats* stats, void* stream);
 
 /* [async] Misfit of the phase field against a target:
  *   L = 1/2 sum_i m_i (phi_i - phi*_i)^2 with the lumped nodal mass

@@ -90,7 +90,7 @@ _SIGS = {
     "pf_destroy": (ctypes.c_int, [_VP]),
     "pf_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(pf_params)]),
     "pf_num_nodes": (ctypes.c_longlong, [_VP]),
-    "pf_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "pf_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pf_theta_explicit": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "pf_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP]),
     "pf_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -106,6 +106,8 @@ _SIGS = {
                                  ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
                                        ctypes.POINTER(pf_solver_stats), _VP]),
+    "pf_adjoint_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(pf_solver_opts),
+                                        ctypes.POINTER(pf_solver_stats), _VP]),
     "pf_misfit": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pf_dot": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "pf_set_alloy": (ctypes.c_int, [_VP, ctypes.POINTER(pf_alloy_params)]),
@@ -239,9 +241,9 @@ class Problem:
         _check(load().pf_set_params(self.h, ctypes.byref(params)), "pf_set_params")
         self.params = params
 
-    def pf_residual(self, U, Uprev, F, stream=None):
-        _check(load().pf_residual(self.h, self._v(U), self._v(Uprev), self._v(F), _stream(stream)),
-               "pf_residual")
+    def pf_residual(self, U, Uprev, F, rhs=None, stream=None):
+        _check(load().pf_residual(self.h, self._v(U), self._v(Uprev), self._v(rhs), self._v(F),
+                                  _stream(stream)), "pf_residual")
         return F
 
     def pf_theta_explicit(self, Uprev, Uprev2, E, stream=None):
@@ -309,6 +311,14 @@ class Problem:
         _check(load().pf_adjoint_step(self.h, self._v(U), self._v(Uprev), self._v(mu), self._v(lam),
                                       self._v(mu_prev), self._v(gparams, 2), ctypes.byref(o),
                                       ctypes.byref(st), _stream(stream)), "pf_adjoint_step")
+        return st.as_dict()
+
+    def pf_adjoint_solve(self, U, Uprev, rhs, lam, opts=None, stream=None):
+        o = opts if opts is not None else default_opts()
+        st = pf_solver_stats()
+        _check(load().pf_adjoint_solve(self.h, self._v(U), self._v(Uprev), self._v(rhs), self._v(lam),
+                                       ctypes.byref(o), ctypes.byref(st), _stream(stream)),
+               "pf_adjoint_solve")
         return st.as_dict()
 
     def pf_set_alloy(self, alloy: pf_alloy_params):

@@ -30,6 +30,17 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Start of a [sync] call's clock: the stream is drained first, so that work the
+// caller queued before the call is not counted in its t_total_ms.
+int clock_start(hipStream_t s, double* t0) {
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    set_error("hipStreamSynchronize failed before the call's work");
+    return PF_ERR_HIP;
+  }
+  *t0 = now_ms();
+  return PF_OK;
+}
+
 __global__ void k_misfit(Geo G, const double2* __restrict__ U, const double* __restrict__ target,
                          double2* __restrict__ g, double* __restrict__ partials) {
   __shared__ double sh[256];
@@ -100,6 +111,8 @@ __global__ void k_theta_hist(Geo G, const double2* __restrict__ Un,
   }
 }
 
+}  // namespace
+
 int check_vec(const void* p, const char* name) {
   if (!p) {
     set_error(std::string("null device pointer: ") + name);
@@ -153,6 +166,8 @@ int check_params(const pf_params* p) {
   }
   return PF_OK;
 }
+
+namespace {
 
 int check_opts(const pf_problem* pb, const pf_solver_opts* o) {
   if (!o) {
@@ -597,7 +612,8 @@ int evolve_loop(pf_problem* pb, double* states, int steps, pf_solver_stats* stat
   const long long n = pb->n_dof;
   pf_solver_stats acc;
   stats_reset(&acc);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(s, &t0));
   for (int k = 0; k < steps; ++k) {
     double* prev = states + (long long)k * n;
     double* next = prev + n;
@@ -834,7 +850,8 @@ int pf_set_params(pf_problem* pb, const pf_params* p) {
 
 long long pf_num_nodes(const pf_problem* pb) { return pb ? pb->geo.n_nodes : -1; }
 
-int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F, void* stream) {
+int pf_residual(pf_problem* pb, const double* U, const double* Uprev, const double* rhs, double* F,
+                void* stream) {
   clear_stale_error();
   if (!pb) {
     set_error("handle is NULL");
@@ -844,8 +861,13 @@ int pf_residual(pf_problem* pb, const double* U, const double* Uprev, double* F,
   PF_TRY(check_vec(U, "U"));
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(F, "F"));
-  return launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
-                                nullptr, S(stream));
+  if (rhs) PF_TRY(check_vec(rhs, "rhs"));
+  hipStream_t s = S(stream);
+  PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
+                                nullptr, s));
+  // F - b: fma(1, F, -b) rounds once, so the result is the exact difference rounded
+  if (rhs) PF_TRY(blas_axpby(1.0, F, -1.0, rhs, F, pb->n_dof, s));
+  return PF_OK;
 }
 
 int pf_jvp(pf_problem* pb, const double* U, const double* Uprev, const double* v, const double* F0,
@@ -952,7 +974,8 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
   PF_TRY(check_vec(x, "x"));
   hipStream_t s = S(stream);
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(s, &t0));
   double* F = pb->tmp_vec[0];
   int kind = transpose ? 2 : (opts->jv_mode == PF_JV_FD ? 0 : 1);
   if (kind == 0)
@@ -982,7 +1005,8 @@ int pf_newton_step(pf_problem* pb, const double* Uprev, double* U, const pf_solv
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(S(stream), &t0));
   int rc = newton_impl(pb, Uprev, nullptr, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;
@@ -1004,7 +1028,8 @@ int pf_newton_step_theta(pf_problem* pb, const double* Uprev2, const double* Upr
   PF_TRY(check_vec(U, "U"));
   if (pb->params.theta != 1.0) PF_TRY(check_vec(Uprev2, "Uprev2"));
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(S(stream), &t0));
   const int rc = thermal_step_impl(pb, Uprev2, Uprev, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;
@@ -1074,7 +1099,8 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   }
   hipStream_t s = S(stream);
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(s, &t0));
   PF_TRY(pc_setup(pb, U, opts->pc, opts->pc_precision, s));
   Op op{pb, U, Uprev, nullptr, 2};
   int its = 0;
@@ -1095,6 +1121,36 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   PF_HIP_CHECK(hipStreamSynchronize(s));
   if (stats) stats->t_total_ms = now_ms() - t0;
   return PF_OK;
+}
+
+int pf_adjoint_solve(pf_problem* pb, const double* U, const double* Uprev, const double* rhs,
+                     double* lam, const pf_solver_opts* opts, pf_solver_stats* stats, void* stream) {
+  clear_stale_error();
+  if (!pb) {
+    set_error("handle is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PF_TRY(require_model(pb, 0));
+  PF_TRY(check_opts(pb, opts));
+  PF_TRY(check_vec(U, "U"));
+  PF_TRY(check_vec(Uprev, "Uprev"));
+  PF_TRY(check_vec(rhs, "rhs"));
+  PF_TRY(check_vec(lam, "lam"));
+  hipStream_t s = S(stream);
+  stats_reset(stats);
+  double t0;
+  PF_TRY(clock_start(s, &t0));
+  PF_TRY(pc_setup(pb, U, opts->pc, opts->pc_precision, s));
+  Op op{pb, U, Uprev, nullptr, 2};
+  int its = 0;
+  const int rc = fgmres(pb, op, rhs, lam, opts->tau_r, *opts, &its, s);
+  if (stats) {
+    stats->gmres_its_total = its;
+    stats->gmres_its[0] = its;
+    stats->status = rc;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return rc;
 }
 
 int pf_set_alloy(pf_problem* pb, const pf_alloy_params* a) {
@@ -1216,7 +1272,8 @@ int pf_alloy_step(pf_problem* pb, const double* Uprev2, const double* Uprev, dou
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(S(stream), &t0));
   int rc = alloy_step_impl(pb, Uprev2, Uprev, t_prev, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;
@@ -1359,7 +1416,8 @@ int pf_fg_step(pf_problem* pb, const double* Uprev2, const double* Uprev, double
   PF_TRY(check_vec(Uprev, "Uprev"));
   PF_TRY(check_vec(U, "U"));
   stats_reset(stats);
-  const double t0 = now_ms();
+  double t0;
+  PF_TRY(clock_start(S(stream), &t0));
   int rc = fg_step_impl(pb, Uprev2, Uprev, U, *opts, stats, S(stream));
   if (stats) {
     stats->status = rc;

@@ -451,20 +451,21 @@ Tiles tiles_for(const Geo& G) {
   return T;
 }
 
+// side: the tile-face partial sums, fused3_side_len(G) doubles (the first
+// tiles x (KZ + 1) x PN x NO of them are used).
 template <int MODE>
-int launch_mode(pf_problem* pb, const double* U, const double* Uprev, const double* v,
+int launch_mode(const Geo& G, double* side, const double* U, const double* Uprev, const double* v,
                 const double* F0, const double* eps_dev, double* out0, double* out1,
                 double* vjp_part, double* coef, hipStream_t s) {
-  const Geo& G = pb->geo;
   const Tiles T = tiles_for(G);
   const unsigned nt = (unsigned)(T.ntx * T.nty * T.ntz);
   auto d2 = [](const double* p) { return reinterpret_cast<const double2*>(p); };
   hipLaunchKernelGGL((k_fused3<MODE>), dim3(nt), dim3(kThreads), 0, s, G, T, d2(U), d2(Uprev),
                      d2(v), eps_dev, d2(F0), reinterpret_cast<double2*>(out0),
-                     reinterpret_cast<double2*>(out1), pb->side_buf, vjp_part, coef);
+                     reinterpret_cast<double2*>(out1), side, vjp_part, coef);
   PF_HIP_CHECK(hipGetLastError());
   const unsigned nb = (unsigned)(((long long)G.nn[0] * G.nn[1] + 255) / 256);
-  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb, G.nn[2]), dim3(256), 0, s, G, T, pb->side_buf, d2(F0),
+  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nb, G.nn[2]), dim3(256), 0, s, G, T, side, d2(F0),
                      eps_dev, reinterpret_cast<double2*>(out0), reinterpret_cast<double2*>(out1));
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
@@ -482,22 +483,35 @@ int fused3_tiles(const Geo& G) {
   return T.ntx * T.nty * T.ntz;
 }
 
+long long fused3_residual_side_len(const Geo& G) {
+  const Tiles T = tiles_for(G);
+  return (long long)T.ntx * T.nty * T.ntz * (KZ + 1) * PN * ModeInfo<MODE_RES>::NO;
+}
+
+int launch_fused3_residual(const Geo& G, double* side, const double* U, const double* Uprev,
+                           double* F, hipStream_t s) {
+  return launch_mode<MODE_RES>(G, side, U, Uprev, nullptr, nullptr, nullptr, F, nullptr, nullptr,
+                               nullptr, s);
+}
+
 int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
                   const double* F0, const double* eps_dev, double* out0, double* out1,
                   double* vjp_part, double* coef, hipStream_t s) {
+  const Geo& G = pb->geo;
+  double* side = pb->side_buf;
   switch (mode) {
     case MODE_RES:
-      return launch_mode<MODE_RES>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
+      return launch_mode<MODE_RES>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, coef, s);
     case MODE_FD:
-      return launch_mode<MODE_FD>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+      return launch_mode<MODE_FD>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     case MODE_JVP:
-      return launch_mode<MODE_JVP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+      return launch_mode<MODE_JVP>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     case MODE_VJPU:
-      return launch_mode<MODE_VJPU>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+      return launch_mode<MODE_VJPU>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     case MODE_VJPP:
-      return launch_mode<MODE_VJPP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+      return launch_mode<MODE_VJPP>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
     default:
-      return launch_mode<MODE_VJP>(pb, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
+      return launch_mode<MODE_VJP>(G, side, U, Uprev, v, F0, eps_dev, out0, out1, vjp_part, nullptr, s);
   }
 }
 

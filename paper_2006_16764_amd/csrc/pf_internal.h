@@ -101,6 +101,20 @@ int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev
                   const double* F0, const double* eps_dev, double* out0, double* out1,
                   double* vjp_part, double* coef, hipStream_t s);
 
+// The thermal residual alone with caller-provided scratch: 3-D through the
+// fused kernel with side buffer `side` (fused3_residual_side_len(G) doubles),
+// 2-D through the two-pass kernels with element buffer `elem`
+// (residual2_elem_len(G) doubles).  Same kernels as pf_residual.
+long long fused3_residual_side_len(const Geo& G);
+int launch_fused3_residual(const Geo& G, double* side, const double* U, const double* Uprev,
+                           double* F, hipStream_t s);
+long long residual2_elem_len(const Geo& G);
+int launch_residual2(const Geo& G, double* elem, const double* U, const double* Uprev, double* F,
+                     hipStream_t s);
+// Host-side argument checks shared by the entry points (pf_abi.hip).
+int check_params(const pf_params* p);
+int check_vec(const void* p, const char* name);
+
 // Launch helpers (defined in pf_residual.hip).
 // coef (optional, residual mode only): receives the cell mean of a(grad phi)^2,
 // the coefficient of the preconditioner's phi block.

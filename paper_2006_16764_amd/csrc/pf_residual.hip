@@ -199,6 +199,22 @@ int launch_dim(pf_problem* pb, int mode, const double* U, const double* Uprev, c
 
 }  // namespace
 
+long long residual2_elem_len(const Geo& G) { return (long long)2 * 4 * G.n_elems; }
+
+int launch_residual2(const Geo& G, double* elem, const double* U, const double* Uprev, double* F,
+                     hipStream_t s) {
+  const unsigned eb = (unsigned)((G.n_elems + kElemBlock - 1) / kElemBlock);
+  const dim3 nb((unsigned)(((long long)G.nn[0] * G.nn[1] + 255) / 256), (unsigned)G.nn[2]);
+  hipLaunchKernelGGL((k_elem<2, MODE_RES>), dim3(eb), dim3(kElemBlock), 0, s, G,
+                     reinterpret_cast<const double2*>(U), reinterpret_cast<const double2*>(Uprev),
+                     nullptr, nullptr, elem, nullptr, nullptr);
+  PF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_gather<2, 2>), dim3(nb), dim3(256), 0, s, G, elem,
+                     reinterpret_cast<double2*>(F), nullptr, nullptr, nullptr, 0);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
 int launch_gather2(pf_problem* pb, double* out0, const double* F0, const double* eps_dev, int fd,
                    hipStream_t s) {
   const Geo& G = pb->geo;

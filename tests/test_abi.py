@@ -83,6 +83,6 @@ def test_host_side_argument_validation_without_gpu():
         assert b"theta" in lib.pf_last_error()
     good = binding.make_params(2, [8, 8], [1.0, 1.0], 0.1, 0.02, 1.6, 2.0)
     assert lib.pf_create(ctypes.byref(good), 0, ctypes.byref(h)) == binding.PF_ERR_INVALID_ARG
-    assert lib.pf_residual(None, None, None, None, None) == binding.PF_ERR_INVALID_ARG
+    assert lib.pf_residual(None, None, None, None, None, None) == binding.PF_ERR_INVALID_ARG
     o = binding.default_opts()
     assert (o.eta0, o.eta_min, o.eta_max, o.omega, o.gamma, o.tau_a) == (0.1, 1e-6, 0.01, 1.5, 0.9, 0.0)

@@ -27,6 +27,7 @@ import torch
 from oracle import deriv, fem, precond, solvers
 from oracle.fem import Mesh, Params
 from paper_2006_16764_amd import inputs
+from parity import check, check_increment
 
 pytestmark = pytest.mark.gpu
 
@@ -97,19 +98,19 @@ def test_residual_family_on_edge_meshes(case):
     Ud, Upd = dev(U), dev(Up)
     F = pb.new_vector()
     pb.pf_residual(Ud, Upd, F)
-    assert rel(host(F), fem.residual(mesh, U, Up, p)) < 1e-12
+    check(host(F), fem.residual(mesh, U, Up, p), 1e-12, f"edge residual {case}")
     Jv = pb.new_vector()
     pb.pf_jvp(Ud, Upd, dev(v), Jv, mode=binding.PF_JV_ANALYTIC)
     ref = deriv.jvp(mesh, U, Up, v, p)
-    assert rel(host(Jv), ref) < 1e-12
+    check(host(Jv), ref, 1e-12, f"edge analytic Jv {case}")
     pb.pf_jvp(Ud, Upd, dev(v), Jv, mode=binding.PF_JV_FD)
     assert rel(host(Jv), ref) < 2e-6
     gU, gP = pb.new_vector(), pb.new_vector()
     gp = torch.zeros(2, dtype=torch.float64, device="cuda")
     pb.pf_vjp(Ud, Upd, dev(w), gU, gP, gp)
     rgU, rgP, rge, rgl = deriv.vjp(mesh, U, Up, w, p)
-    assert rel(host(gU), rgU) < 1e-12
-    assert rel(host(gP), rgP) < 1e-12
+    check(host(gU), rgU, 1e-12, f"edge VJP gU {case}")
+    check(host(gP), rgP, 1e-12, f"edge VJP gUprev {case}")
     gpn = gp.cpu().numpy()
     assert abs(gpn[0] - rge) < 1e-11 * max(1.0, abs(rge))
     assert abs(gpn[1] - rgl) < 1e-11 * max(1.0, abs(rgl))
@@ -145,4 +146,5 @@ def test_newton_step_on_edge_meshes(case, jv):
     assert st["f_final"] < 1e-10 * st["f0"]
     ref, _ = solvers.newton(mesh, Up, Up, p, tau_r=1e-13)
     assert rel(host(Ug), ref) < 1e-8, st
+    check_increment(host(Ug), ref, Up, 1e-8, f"edge Newton {case} {jv}")
     assert pb.close() == 0

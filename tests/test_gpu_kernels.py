@@ -2,7 +2,8 @@
 
 Every comparison runs the HIP path through the C ABI and the FP64 CPU oracle on
 the same seeded inputs.  Residual, analytic Jv and VJP must agree to 1e-12
-relative (norm-wise); the FD Jv to its truncation error.
+relative, norm-wise and per field elementwise (largest difference over the
+field's largest entry); the FD Jv to its truncation error.
 """
 import dataclasses
 import math
@@ -15,6 +16,7 @@ import torch
 from oracle import deriv, fem, precond
 from oracle.fem import Mesh, Params
 from paper_2006_16764_amd import inputs
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +76,23 @@ def test_residual_parity(case, kind):
     F = pb.new_vector()
     pb.pf_residual(dev(U), dev(Up), F)
     ref = fem.residual(mesh, U, Up, p)
-    assert rel(host(F), ref) < 1e-12
+    check(host(F), ref, 1e-12, f"residual {case} {kind}")
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]], ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
+def test_residual_with_load_parity(case):
+    """pf_residual with a load vector b returns F(U; U^n) - b (the manufactured-
+    solution form of the oracle's Newton, solvers.newton(load=b))."""
+    note(f"residual with load {case}")
+    mesh, p, U, Up, pb = setup_case(case, 4)
+    b = inputs.random_vector(mesh.n_nodes, 21)
+    F = pb.new_vector()
+    pb.pf_residual(dev(U), dev(Up), F, rhs=dev(b))
+    check(host(F), fem.residual(mesh, U, Up, p) - b, 1e-12, f"residual - load {case}")
+    F0 = pb.new_vector()
+    pb.pf_residual(dev(U), dev(Up), F0)
+    # one rounding of the exact difference
+    assert np.array_equal(host(F), host(F0) - b)
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
@@ -86,7 +104,7 @@ def test_analytic_jvp_parity(case):
     Jv = pb.new_vector()
     pb.pf_jvp(dev(U), dev(Up), dev(v), Jv, mode=binding.PF_JV_ANALYTIC)
     ref = deriv.jvp(mesh, U, Up, v, p)
-    assert rel(host(Jv), ref) < 1e-12
+    check(host(Jv), ref, 1e-12, f"analytic Jv {case}")
 
 
 @pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"{c[0]}d-{'x'.join(map(str, c[1]))}")
@@ -120,8 +138,8 @@ def test_vjp_parity(case):
     gp = torch.zeros(2, dtype=torch.float64, device="cuda")
     pb.pf_vjp(dev(U), dev(Up), dev(w), gU, gP, gp)
     rgU, rgP, rge, rgl = deriv.vjp(mesh, U, Up, w, p)
-    assert rel(host(gU), rgU) < 1e-12
-    assert rel(host(gP), rgP) < 1e-12
+    check(host(gU), rgU, 1e-12, f"VJP gU {case}")
+    check(host(gP), rgP, 1e-12, f"VJP gUprev {case}")
     gpn = gp.cpu().numpy()
     assert abs(gpn[0] - rge) < 1e-12 * max(1.0, abs(rge)) * 10
     assert abs(gpn[1] - rgl) < 1e-12 * max(1.0, abs(rgl)) * 10

@@ -2,7 +2,8 @@
 
 Linear solves are compared with the oracle's sparse direct solve, Newton steps
 with the oracle's exact-Jacobian Newton (1e-8 relative after convergence to
-1e-10), gradients with the oracle's direct adjoint.  Failure paths are forced
+1e-10, on the increment U - U^n and per field), gradients with the oracle's
+direct adjoint.  Failure paths are forced
 from the host.
 """
 import dataclasses
@@ -17,6 +18,7 @@ import torch
 from oracle import deriv, fem, solvers
 from oracle.fem import Mesh, Params
 from paper_2006_16764_amd import inputs
+from parity import check, check_increment
 
 pytestmark = pytest.mark.gpu
 
@@ -113,6 +115,7 @@ def test_newton_step_matches_oracle(jv, pc):
     assert st["f_final"] < 1e-10 * st["f0"]
     ref, ost = solvers.newton(mesh, U0, U0, p, tau_r=1e-13)
     assert rel(host(U), ref) < 1e-8, (st, ost)
+    check_increment(host(U), ref, U0, 1e-8, f"Newton jv={jv} pc={pc}")
     # certified by the oracle's own residual
     Fo = fem.residual(mesh, host(U), U0, p)
     assert np.linalg.norm(Fo) < 1e-9 * st["f0"]
@@ -128,9 +131,9 @@ def test_newton_3d_mixed_precision_equals_fp64():
         st = pb.pf_newton_step(dev(U0), U, binding.default_opts(pc_precision=prec))
         res[prec] = (host(U), st)
     a, b = res[binding.PF_FP64][0], res[binding.PF_FP32][0]
-    assert rel(b, a) < 1e-8, (res[0][1], res[1][1])
+    check_increment(b, a, U0, 1e-8, "FP32 vs FP64 V-cycle Newton")
     ref, _ = solvers.newton(mesh, U0, U0, p, tau_r=1e-13)
-    assert rel(a, ref) < 1e-8
+    check_increment(a, ref, U0, 1e-8, "FP64 V-cycle Newton vs oracle")
 
 
 def test_evolve_matches_oracle_time_stepping():
@@ -145,6 +148,30 @@ def test_evolve_matches_oracle_time_stepping():
     got = states.view(steps + 1, -1).cpu().numpy()
     for k in range(steps + 1):
         assert rel(got[k].reshape(-1, 2), ref[k]) < 1e-8, (k, st)
+        if k:
+            check_increment(got[k], ref[k], ref[k - 1], 1e-8, f"evolve step {k}")
+
+
+@pytest.mark.parametrize("pc", ["gmg64", "gmg32"])
+def test_adjoint_solve_matches_direct_transposed_solve(pc):
+    """pf_adjoint_solve sets the preconditioner up at U itself and solves
+    F'(U)^T lam = rhs; the oracle solves the same system directly."""
+    note(f"adjoint solve pc={pc}")
+    from paper_2006_16764_amd import binding
+    w, mesh, p, U0, pb = seed_problem("seed2d_64", 32, dt=0.5)
+    rng = np.random.default_rng(4)
+    U = U0 + 0.05 * rng.standard_normal(U0.shape)
+    b = inputs.random_vector(mesh.n_nodes, 6)
+    opts = binding.default_opts(tau_r=1e-12, pc=binding.PF_PC_GMG,
+                                pc_precision=binding.PF_FP64 if pc == "gmg64" else binding.PF_FP32)
+    lam = pb.new_vector()
+    st = pb.pf_adjoint_solve(dev(U), dev(U0), dev(b), lam, opts)
+    J = deriv.jacobian(mesh, U, U0, p)
+    ref = spla.spsolve(J.T.tocsc(), b.reshape(-1)).reshape(-1, 2)
+    check(host(lam), ref, 1e-9, f"adjoint solve {pc}")
+    r = b.reshape(-1) - J.T @ host(lam).reshape(-1)
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(b), st
+    assert 0 < st["gmres_its_total"] < 300
 
 
 def test_adjoint_gradient_matches_oracle():
@@ -248,7 +275,7 @@ def test_invalid_arguments_are_rejected():
         pb.pf_newton_step(dev(U0), dev(U0), binding.default_opts(gmres_m=100))
     assert e.value.code == binding.PF_ERR_INVALID_ARG
     lib = binding.load()
-    assert lib.pf_residual(pb.h, None, None, None, None) == binding.PF_ERR_INVALID_ARG
+    assert lib.pf_residual(pb.h, None, None, None, None, None) == binding.PF_ERR_INVALID_ARG
     # the binding checks the sizes the library will touch before calling it
     short = torch.zeros(pb.n_dof - 2, dtype=torch.float64, device="cuda")
     F = pb.new_vector()
