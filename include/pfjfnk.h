@@ -73,10 +73,13 @@ extern "C" {
 
 /* Model and mesh.  dim = 2 or 3; n[k] >= 1 elements per axis (n[2] ignored
  * in 2-D); half_width[k] > 0.  dt > 0, D > 0, delta2 > 0 (regularises the
- * anisotropy where grad phi = 0; 1e-16 is the default reading.  Where grad phi
- * vanishes identically in an element, a gradient perturbation above
- * sqrt(delta2) moves a by O(eps4), so FD products or the FP32 V-cycle can stall
- * Newton at such exactly symmetric states); theta in
+ * anisotropy where grad phi = 0, where Eq. gs is undefined; 1e-8 is the
+ * default reading: a(g) is then smooth at the scale of the gradient
+ * perturbations of FD products and of the FP32 preconditioner (about 1e-8),
+ * which keeps Newton convergent at exactly symmetric states, and moves a on
+ * the interface by about eps4 delta2/|grad phi|^2 ~ 1e-9.  Values near the
+ * size of those perturbations, such as 1e-16, can stall Newton's line search
+ * there); theta in
  * (0, 1]: the time weight of Eq. dpf (1 backward Euler, 1/2 the trapezoidal
  * or Crank-Nicolson rule).  order: Lagrange element order, 1 (bilinear /
  * trilinear; 0 is read as 1) or 2 (biquadratic, 2-D, free-growth model only):
@@ -164,6 +167,24 @@ long long pf_num_nodes(const pf_problem* pb);
  * doubles.  F must not alias U, Uprev or rhs. */
 int pf_residual(pf_problem* pb, const double* U, const double* Uprev, const double* rhs, double* F,
                 void* stream);
+
+/* [async] pf_residual without a handle and without any device allocation,
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  F =
+ * F(U; Uprev) for the thermal model of params (order-1 elements, 2-D or 3-D),
+ * bit for bit equal to pf_residual on a handle of the same params.  The
+ * kernels' scratch (3-D: tile-face partial sums, 2-D: element vectors) is a
+ * fixed array of 64 MiB inside the library, one copy per device, held from the
+ * first call on that device until the process ends; its device address is
+ * looked up on that first call.  Meshes whose scratch exceeds it -- beyond
+ * about 853 tiles of 16^3 elements in 3-D (128^3 fits), or 2^20 elements in
+ * 2-D (1024^2 fits) -- are rejected with PF_ERR_INVALID_ARG before anything is
+ * launched.  All calls on one device share that array: calls that overlap in
+ * time on one device (other streams or threads) race and must not be issued.
+ * The array holds the last call's partial sums; nothing in it needs clearing.
+ * U, Uprev, F: device, 2*n_nodes doubles; F must not alias U or Uprev. */
+int pf_residual_noalloc(const pf_params* params, const double* U, const double* Uprev, double* F,
+                        void* stream);
 
 /* [async] E = E(Uprev, Uprev2), the part of the step residual fixed by the two
  * previous states (Eqs. dpf, dtemp and the lagged half of the rate of Eq.

@@ -66,7 +66,7 @@ class AlloyParams:
     x_iso: float = 0.0
     v_pull: float = 0.0
     theta: float = 0.5
-    delta2: float = 1e-16
+    delta2: float = 1e-8
 
 
 def g4(x, t, p: AlloyParams):

@@ -63,7 +63,7 @@ class Params:
     eps4: float
     lam: float
     D: float
-    delta2: float = 1e-16
+    delta2: float = 1e-8
     theta: float = 1.0
 
 

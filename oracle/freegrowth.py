@@ -57,7 +57,7 @@ class FGParams:
     Lcp: float
     Tm: float
     theta: float = 0.5
-    delta2: float = 1e-16
+    delta2: float = 1e-8
 
 
 def lagrange_1d(p: int, xi: float) -> Tuple[np.ndarray, np.ndarray]:

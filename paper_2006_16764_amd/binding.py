@@ -91,6 +91,7 @@ _SIGS = {
     "pf_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(pf_params)]),
     "pf_num_nodes": (ctypes.c_longlong, [_VP]),
     "pf_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pf_residual_noalloc": (ctypes.c_int, [ctypes.POINTER(pf_params), _VP, _VP, _VP, _VP]),
     "pf_theta_explicit": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "pf_jvp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP]),
     "pf_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -190,7 +191,7 @@ def default_opts(**kw) -> pf_solver_opts:
     return o
 
 
-def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-16, theta=1.0, order=1) -> pf_params:
+def make_params(dim, n, half_width, dt, eps4, lam, D, delta2=1e-8, theta=1.0, order=1) -> pf_params:
     p = pf_params()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -401,6 +402,17 @@ class Problem:
 
     def pf_dot(self, x, y, out_dev, stream=None):
         _check(load().pf_dot(self.h, self._v(x), self._v(y), self._v(out_dev, 1), _stream(stream)), "pf_dot")
+
+
+def pf_residual_noalloc(params: pf_params, U, Uprev, F, stream=None):
+    """F = F(U; Uprev) with no handle and no device allocation (the library's
+    fixed scratch array); same arguments as Problem.pf_residual plus params."""
+    n = 1
+    for k in range(params.dim):
+        n *= params.n[k] + 1
+    _check(load().pf_residual_noalloc(ctypes.byref(params), _ptr(U, 2 * n), _ptr(Uprev, 2 * n),
+                                      _ptr(F, 2 * n), _stream(stream)), "pf_residual_noalloc")
+    return F
 
 
 def problem_for(w, gmres_m_max: int = 30, eps4=None, lam=None, theta=1.0) -> Problem:

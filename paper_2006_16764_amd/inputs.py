@@ -44,7 +44,7 @@ class Workload:
     u0: float
     seed: int
     steps: int
-    delta2: float = 1e-16
+    delta2: float = 1e-8
 
     @property
     def h(self) -> float:
@@ -226,7 +226,7 @@ class AlloyWorkload:
     eps4: float = 0.01
     lam: float = 10.0
     u0: float = -1.0
-    delta2: float = 1e-16
+    delta2: float = 1e-8
 
     @property
     def half_width(self) -> Tuple[float, ...]:
@@ -320,7 +320,7 @@ class FreeGrowthWorkload:
     Tm: float = 1.0
     undercooling: float = 0.55
     r0: float = 0.3
-    delta2: float = 1e-16
+    delta2: float = 1e-8
 
     @property
     def Gamma(self) -> float:

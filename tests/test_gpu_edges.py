@@ -9,13 +9,11 @@ the VJP must match the oracle to 1e-12, the FD Jv to its truncation error, the
 V-cycle to 1e-12 (FP64) / 2e-5 (FP32), and Newton steps to 1e-8 after
 convergence to 1e-10.
 
-The seed is placed off the mesh centre.  A seed at the centre of a mesh that is
-symmetric about one element makes grad(phi) vanish identically in that element;
-there the anisotropy, regularised with Q = |grad phi|^2 + delta^2 (delta = 1e-8),
-changes by O(eps4) under gradient perturbations larger than delta, which the FD
-products and the FP32 preconditioner produce, so Newton's line search can fail
-at such a state.  That is a property of the regularised residual (the oracle's
-exact-Jacobian Newton keeps the symmetry exactly), not of the solver.
+The seed is placed off the mesh centre in these cases; a separate case puts it
+at the centre of odd meshes, where grad(phi) vanishes identically in the middle
+element.  There the anisotropy's regularisation (Q = |grad phi|^2 + delta2,
+delta2 = 1e-8) must be smooth at the scale of the FD products' and the FP32
+preconditioner's perturbations; that Newton case runs with both.
 """
 import math
 import sys
@@ -68,16 +66,17 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
-def setup(case, seed):
+def setup(case, seed, centred=False):
     """A smooth seed (tanh profile of radius 0.3 of the smallest half-width,
-    centred off the mesh centre) plus 5 % noise as U, the profile as U^n."""
+    centred off the mesh centre unless centred) plus 5 % noise as U, the
+    profile as U^n."""
     from paper_2006_16764_amd import binding
     dim, n = case
     L = tuple(0.4 * k for k in n)
     mesh = Mesh(dim, n, L)
     p = Params(dt=0.2, eps4=0.05, lam=1.6, D=2.0)
     X = mesh.coords()
-    c = np.array([0.15, -0.09, 0.05][:dim]) * np.array(L)
+    c = np.zeros(dim) if centred else np.array([0.15, -0.09, 0.05][:dim]) * np.array(L)
     r = np.sqrt(((X - c) ** 2).sum(axis=1))
     Up = np.zeros((mesh.n_nodes, 2))
     Up[:, 0] = -np.tanh((r - 0.3 * min(L)) / math.sqrt(2.0))
@@ -147,4 +146,24 @@ def test_newton_step_on_edge_meshes(case, jv):
     ref, _ = solvers.newton(mesh, Up, Up, p, tau_r=1e-13)
     assert rel(host(Ug), ref) < 1e-8, st
     check_increment(host(Ug), ref, Up, 1e-8, f"edge Newton {case} {jv}")
+    assert pb.close() == 0
+
+
+# odd meshes with the seed at their centre: grad(phi) = 0 in the middle element
+SYMMETRIC = [(3, (1, 1, 1)), (3, (3, 3, 3)), (3, (17, 17, 17)), (2, (1, 7)), (2, (9, 9))]
+
+
+@pytest.mark.parametrize("case", SYMMETRIC, ids=ident)
+@pytest.mark.parametrize("jv", ["fd", "analytic"])
+def test_newton_step_at_symmetric_states(case, jv):
+    note(f"symmetric newton {case} {jv}")
+    from paper_2006_16764_amd import binding
+    mesh, p, U, Up, pb = setup(case, 1, centred=True)
+    opts = binding.default_opts(tau_r=1e-10, pc=binding.PF_PC_GMG, pc_precision=binding.PF_FP32,
+                                jv_mode=binding.PF_JV_FD if jv == "fd" else binding.PF_JV_ANALYTIC)
+    Ug = dev(Up)
+    st = pb.pf_newton_step(dev(Up), Ug, opts)
+    assert st["f_final"] < 1e-10 * st["f0"], st
+    ref, _ = solvers.newton(mesh, Up, Up, p, tau_r=1e-13)
+    check_increment(host(Ug), ref, Up, 1e-8, f"symmetric Newton {case} {jv}")
     assert pb.close() == 0

@@ -174,9 +174,11 @@ def test_cell_coefficient_is_the_time_term_mobility(dim, n, L):
                                               ((0, 0, 1), lambda e: 1 + e),
                                               ((0, 1, -1), lambda e: 1 - e)])
 def test_cell_coefficient_of_a_linear_field(direction, factor):
+    # closed forms of Eq. gs: exact without the regularisation of a vanishing
+    # gradient (delta2 = 0; the gradient is nowhere zero here)
     eps = 0.045
     mesh = Mesh(3, [3, 4, 2], [1.0, 1.4, 0.6])
-    p = Params(dt=0.2, eps4=eps, lam=1.6, D=2.0)
+    p = Params(dt=0.2, eps4=eps, lam=1.6, D=2.0, delta2=0.0)
     X = mesh.coords()
     n = np.array(direction, dtype=float)
     U = np.stack([0.3 * (X @ n), np.zeros(mesh.n_nodes)], axis=1)
@@ -187,7 +189,7 @@ def test_cell_coefficient_of_a_linear_field(direction, factor):
 def test_cell_coefficient_of_a_linear_field_2d():
     eps = 0.03
     mesh = Mesh(2, [4, 3], [1.0, 0.8])
-    p = Params(dt=0.2, eps4=eps, lam=1.6, D=2.0)
+    p = Params(dt=0.2, eps4=eps, lam=1.6, D=2.0, delta2=0.0)
     X = mesh.coords()
     for th in np.linspace(0.1, 1.4, 6):
         U = np.stack([0.5 * (math.cos(th) * X[:, 0] + math.sin(th) * X[:, 1]), np.zeros(mesh.n_nodes)],
