@@ -1,6 +1,7 @@
 """Benchmark of the matrix-free JFNK phase-field hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload seeds3d_256]
+    python bench.py --probe [--probe-only residual,fd,...] [--probe-reps N]
 
 Workload (default): 3-D Q1 hex mesh 256^3 (257^3 nodes, 33,949,186 unknowns),
 eight seeded diffuse seeds of radius 6, eps4 drawn once from U[0.02, 0.05],
@@ -16,14 +17,28 @@ The JSON line's value is the Jacobian-vector throughput of the whole timed
 region: (number of Jv and VJP applications performed, inside and outside the
 Krylov solves) x unknowns / timed wall time, in MDOF/s.  The roofline object
 is for the element kernel of the residual family, timed live with HIP events
-on its stream.  After the timed region the same Newton step is repeated from
-the same state with the FP64 V-cycle for the mixed-vs-FP64 comparison, one
-Crank-Nicolson (theta = 1/2) step continues from the last two states, the
-CPU oracle is timed on a bounded slab of the same workload, the alloy model
-(directional solidification, 1024 x 256 x 256 elements, theta = 1/2,
-dt = 0.002) takes a warm-up and two timed steps on its own seeded state, and
-the free-growth model takes Crank-Nicolson steps on the paper's 150^2 mesh
-with Q1 and Q2 elements (kernel throughput of Q2 on 2048^2 elements).
+on its stream.  After the timed region:
+  * a plain device copy (the achievable-bandwidth reference);
+  * the same Newton step repeated from the same state with the FP64 V-cycle,
+    compared with the mixed-precision one on the increments U - U^n;
+  * one Crank-Nicolson (theta = 1/2) step from the last two states;
+  * the other workloads at their own shapes: seeds2d_1024 (1000 back-to-back
+    calls of each residual-family kernel, 20 steps dt = 0.5 with the FP64
+    V-cycle), sphere3d_128 (10 steps dt = 0.2, FP64 against FP32 V-cycle),
+    adjoint2d_512 (20-step forward and adjoint through the autograd Function,
+    gradient against central differences);
+  * the CPU oracle certifies the 256^3 mixed-precision Newton solution with its
+    own residual (element slabs in parallel processes) and is timed on the host
+    cores, one process and all of the box's share;
+  * the alloy model (directional solidification, 1024 x 256 x 256 elements,
+    theta = 1/2, dt = 0.002): a warm-up and two timed steps;
+  * the free-growth model: Crank-Nicolson steps on the paper's 150^2 mesh with
+    Q1 and Q2 elements, kernel throughput of Q2 on 2048^2 elements.
+
+--probe launches the hot-path kernels a few times each on the workload and
+exits (for rocprofv3 counter runs): a device copy of --probe-copy-mib MiB first
+(the calibration kernel for hardware byte counters), then --probe-reps calls
+each of the residual, FD Jv, analytic Jv, VJP and the FP32 and FP64 V-cycles.
 """
 from __future__ import annotations
 
@@ -46,12 +61,25 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
     ap.add_argument("--alloy-workload", default="alloy3d_1024x256x256")
     ap.add_argument("--alloy-steps", type=int, default=2)
     ap.add_argument("--no-alloy", action="store_true")
     ap.add_argument("--fg-steps", type=int, default=5)
     ap.add_argument("--no-freegrowth", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the seeds2d_1024, sphere3d_128 and adjoint2d_512 legs")
+    ap.add_argument("--config2-calls", type=int, default=1000)
+    ap.add_argument("--no-certify", action="store_true",
+                    help="skip the oracle's residual at the 256^3 Newton solution")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes (default: the CPUs this process may use, at most 16)")
+    ap.add_argument("--probe", action="store_true", help="launch the kernels for a profiler and exit")
+    ap.add_argument("--probe-only", default="",
+                    help="comma list: copy,residual,fd,jvp,vjp,pc32,pc64; vjpp (the VJP "
+                         "without gU) and vjpu (gU alone) run only when named here")
+    ap.add_argument("--probe-reps", type=int, default=3)
+    ap.add_argument("--probe-copy-mib", type=int, default=1024)
     return ap.parse_args()
 
 
@@ -94,10 +122,11 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
 # HBM bytes moved by one pf_residual call (k_fused3<0> + k_fixup3<0>) on the
 # 256^3 workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# paper_2006_16764_amd.kernel_probe, each scaled by what the same counter
+# `bench.py --probe`, each scaled by what the same counter
 # reads for a plain 1 GiB device copy (FETCH_SIZE reads half the bytes
 # fetched: x2; WRITE_SIZE is exact: x1).  Valid only for the kernel sources
-# whose digest is recorded; reported as null once they change.
+# whose digest is recorded; reported as null once they change (the figure is
+# then re-measured, never re-pointed at new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
     "bytes": 1428670704,
@@ -171,6 +200,8 @@ def main():
     import torch
     from paper_2006_16764_amd import binding, inputs
 
+    if a.probe:
+        return probe(a, binding, inputs, torch)
     w = inputs.workload(a.workload)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -223,17 +254,10 @@ def main():
     newton = [r[0] for r in rec]
     adj = [r[1] for r in rec]
 
-    # ---- dominant kernel, timed live with HIP events on its stream
     def time_call(fn, reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        fn()
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps  # ms
+        return time_call_on(torch, stream, fn, reps)
 
+    # ---- dominant kernel, timed live with HIP events on its stream
     reps = a.kernel_reps
     t_res = time_call(lambda: pb.pf_residual(U, Uprev, F), reps)
     t_fd = time_call(lambda: pb.pf_jvp(U, Uprev, vdir, Jv, mode=binding.PF_JV_FD, F0=F), reps)
@@ -252,9 +276,12 @@ def main():
     achieved = flops / (t_res * 1e-3) / 1e12
     peak = 78.6
     hbm_gbs = BYTES_PER_NODE_RES * w.n_nodes / (t_res * 1e-3) / 1e9
+    copy = device_copy(torch, stream, a.probe_copy_mib)
+    log(f"device copy: {copy['gbs']} GB/s")
 
-    # ---- mixed vs FP64 Newton step from the same state
+    # ---- mixed vs FP64 Newton step from the same state, compared on increments
     cmp = None
+    certify_pair = None
     if not a.no_fp64_compare:
         Ustart = Uprev.clone()
         res = {}
@@ -267,13 +294,20 @@ def main():
             st = pb.pf_newton_step(Ustart, Ux, o)
             torch.cuda.synchronize()
             res[name] = (time.perf_counter() - t1, st, Ux)
-        d = float(torch.linalg.vector_norm(res["fp32_gmg"][2] - res["fp64_gmg"][2])
-                  / torch.linalg.vector_norm(res["fp64_gmg"][2]))
+        d32 = res["fp32_gmg"][2] - Ustart
+        d64 = res["fp64_gmg"][2] - Ustart
+        inc = increment_difference(torch, d32, d64)
         cmp = {k: {"ms": round(1e3 * v[0], 2), "newton_its": v[1]["newton_its"],
                    "gmres_its": v[1]["gmres_its_total"], "f_final_rel": v[1]["f_final"] / v[1]["f0"]}
                for k, v in res.items()}
-        cmp["rel_diff_fp32_vs_fp64"] = d
+        cmp["increment_rel_diff_fp32_vs_fp64"] = inc["rel"]
+        cmp["increment_field_maxabs_fp32_vs_fp64"] = inc["field_maxabs"]
+        cmp["within_1e-8"] = inc["rel"] <= 1e-8 and max(inc["field_maxabs"]) <= 1e-8
         cmp["speedup_mixed"] = round(res["fp64_gmg"][0] / res["fp32_gmg"][0], 3)
+        if not a.no_certify:
+            certify_pair = (res["fp32_gmg"][2].cpu().numpy(), Ustart.cpu().numpy(),
+                            res["fp32_gmg"][1])
+        del d32, d64, res
         log("fp64 comparison done")
 
     # ---- one Crank-Nicolson (theta = 1/2) step continuing from the last state,
@@ -292,20 +326,48 @@ def main():
         cn = {"ms": round(1e3 * (time.perf_counter() - t1), 2), "newton_its": st["newton_its"],
               "gmres_its": st["gmres_its_total"], "f_final_rel": st["f_final"] / st["f0"]}
         pb.set_params(p)
+        del Ux
         log("theta = 1/2 step done")
 
-    # ---- CPU oracle on a bounded slab of the same workload
-    cpu = None
+    host_state = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(w, U.cpu().numpy(), Uprev.cpu().numpy(), vdir.cpu().numpy(), a.cpu_seconds)
+        host_state = (U.cpu().numpy(), Uprev.cpu().numpy(), vdir.cpu().numpy())
+    del F, Jv, gU, gP, mu, lam, mu_prev, U, Uprev, U0, vdir
+    pb.close()
+    torch.cuda.empty_cache()
+
+    # ---- the other workloads at their own shapes
+    configs = None
+    if not a.no_configs:
+        configs = {"seeds2d_1024": config2_leg(a, binding, inputs, torch, dev, time_call),
+                   "sphere3d_128": config3_leg(a, binding, inputs, torch, dev),
+                   "adjoint2d_512": config4_leg(a, binding, inputs, torch, dev)}
+        torch.cuda.empty_cache()
+
+    # ---- the oracle on the host: certification of the 256^3 solution, timings
+    workers = a.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+    pool = None
+    if certify_pair is not None or host_state is not None:
+        import concurrent.futures
+        import multiprocessing
+        pool = concurrent.futures.ProcessPoolExecutor(max_workers=workers,
+                                                      mp_context=multiprocessing.get_context("spawn"))
+    certify = None
+    if certify_pair is not None:
+        certify = certify_leg(pool, workers, w, *certify_pair)
+        del certify_pair
+        log("oracle certification done")
+    cpu = None
+    if host_state is not None:
+        cpu = cpu_baseline(pool, workers, w, *host_state, a.cpu_seconds, certify)
+        del host_state
         log("cpu baseline done")
+    if pool is not None:
+        pool.shutdown()
 
     # ---- alloy model (directional solidification) on its own workload
     alloy = None
     if not a.no_alloy:
-        del F, Jv, gU, gP, mu, lam, mu_prev
-        pb.close()
-        torch.cuda.empty_cache()
         alloy = alloy_leg(a, binding, inputs, torch, dev, time_call, stream)
 
     # ---- free-growth model, Q1 and Q2, at the paper's size and a throughput size
@@ -333,6 +395,7 @@ def main():
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": residual_traffic(w.name),
                      "hbm_gbs_algorithmic": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / 8000.0, 4)},
+        "device_copy": copy,
         "kernels_ms": {"residual": round(t_res, 4), "fd_jv": round(t_fd, 4), "analytic_jv": round(t_jv, 4),
                        "vjp": round(t_vjp, 4), "vjp_gU_only": round(t_vjp_u, 4),
                        "vjp_prev_and_params": round(t_vjp_prev, 4), "pc_setup_fp32": round(t_setup32, 4),
@@ -343,7 +406,10 @@ def main():
         "kernels_fp64": ({k: {"tflops": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12, 2),
                               "frac": round(KERNEL_FLOPS_PER_ELEM_3D[k] * n_elem / (v * 1e-3) / 1e12 / peak, 3)}
                           for k, v in (("residual", t_res), ("fd_jv", t_fd), ("analytic_jv", t_jv),
-                                       ("vjp", t_vjp))} if w.dim == 3 else None),
+                                       ("vjp", t_vjp), ("vjp_gU_only", t_vjp_u),
+                                       ("vjp_prev_and_params", t_vjp_prev))
+                          if k in KERNEL_FLOPS_PER_ELEM_3D}
+                         if w.dim == 3 else None),
         "vcycle_hbm": {name: {"bytes": int(vb), "gbs": round(vb / (t * 1e-3) / 1e9, 1),
                               "frac": round(vb / (t * 1e-3) / 8e12, 3)}
                        for name, vb, t in (("fp32", vcycle_bytes(w.dim, w.n, 4), t_pc32),
@@ -353,12 +419,244 @@ def main():
         "adjoint": [{"gmres": s["gmres_its_total"], "ms": round(s["t_total_ms"], 1)} for s in adj],
         "mixed_vs_fp64": cmp,
         "theta_half_step": cn,
+        "oracle_certification": certify,
+        "configs": configs,
         "cpu_baseline": cpu,
         "alloy": alloy,
         "freegrowth": freegrowth,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def time_call_on(torch, stream, fn, reps):
+    """Mean milliseconds of fn over reps back-to-back calls, HIP events on stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def device_copy(torch, stream, mib, reps=5):
+    """A plain device-to-device copy of mib MiB (read + write), HIP events."""
+    src = torch.empty(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = time_call_on(torch, stream, lambda: dst.copy_(src), reps)
+    moved = 2 * src.numel() * 8
+    del src, dst
+    return {"bytes_moved": moved, "ms": round(ms, 4), "gbs": round(moved / (ms * 1e-3) / 1e9, 1),
+            "frac_of_8tbs": round(moved / (ms * 1e-3) / 8e12, 3)}
+
+
+def increment_difference(torch, d, ref):
+    """rel = |d - ref|_2/|ref|_2 and, per field, max |d - ref| / max |ref| of two
+    interleaved increments (device tensors)."""
+    rel = float(torch.linalg.vector_norm(d - ref) / torch.linalg.vector_norm(ref))
+    dd = (d - ref).view(-1, 2).abs().amax(dim=0)
+    rr = ref.view(-1, 2).abs().amax(dim=0)
+    fm = [float(dd[f] / rr[f]) if float(rr[f]) > 0 else float(dd[f]) for f in range(2)]
+    return {"rel": rel, "field_maxabs": fm}
+
+
+def config2_leg(a, binding, inputs, torch, dev, time_call):
+    """seeds2d_1024 (2-D Q1 1024^2, four seeds R = 5, eps4 = 0.05, u0 = -0.3):
+    back-to-back calls of every residual-family kernel on a perturbed state
+    (HIP events), then 20 backward-Euler steps of dt = 0.5 with the FP64
+    V-cycle and FD products, with their Newton and FGMRES counts."""
+    w = inputs.workload("seeds2d_1024")
+    log(f"{w.name}: n={w.n} dof={w.n_dof}")
+    pb = binding.problem_for(w)
+    n = pb.n_dof
+    U0 = torch.from_numpy(inputs.initial_state_fast(w).reshape(-1)).to(dev)
+    rng = np.random.default_rng(23)
+    U = U0 + torch.from_numpy(1e-3 * rng.standard_normal(n)).to(dev)
+    v = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    F, J, gU, gP = (pb.new_vector() for _ in range(4))
+    gp = torch.zeros(2, dtype=torch.float64, device=dev)
+    calls = a.config2_calls
+    pb.pf_residual(U, U0, F)
+    t = {"residual": time_call(lambda: pb.pf_residual(U, U0, F), calls),
+         "fd_jv": time_call(lambda: pb.pf_jvp(U, U0, v, J, mode=binding.PF_JV_FD, F0=F), calls),
+         "analytic_jv": time_call(lambda: pb.pf_jvp(U, U0, v, J, mode=binding.PF_JV_ANALYTIC), calls),
+         "vjp": time_call(lambda: pb.pf_vjp(U, U0, v, gU, gP, gp), calls)}
+    opts = binding.default_opts(pc=binding.PF_PC_GMG, pc_precision=binding.PF_FP64,
+                                jv_mode=binding.PF_JV_FD, tau_r=1e-10)
+    steps = w.steps
+    S = torch.empty((steps + 1, n), dtype=torch.float64, device=dev)
+    S[0].copy_(U0)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        S[k + 1].copy_(S[k])
+        recs.append(pb.pf_newton_step(S[k], S[k + 1], opts))
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    pb.close()
+    log(f"{w.name} done")
+    return {"workload": f"{w.name}: 2-D Q1 {w.n}^2, {w.n_seeds} seeds R={w.radius}, eps4={w.eps4}, "
+                        f"u0={w.u0}, lambda={w.lam}, D={w.D}, dt={w.dt}",
+            "unknowns": n, "calls_per_kernel": calls,
+            "kernels_ms": {k: round(x, 4) for k, x in t.items()},
+            "kernels_mdofs": {k: round(n / (x * 1e-3) / 1e6, 1) for k, x in t.items()},
+            "steps": {"count": steps, "dt": w.dt, "preconditioner": "FP64 GMG", "jv": "FD",
+                      "ms_per_step": round(ms, 2),
+                      "newton_its": [r["newton_its"] for r in recs],
+                      "gmres_its": [r["gmres_its_total"] for r in recs],
+                      "f_final_rel_max": max(r["f_final"] / r["f0"] for r in recs)}}
+
+
+def config3_leg(a, binding, inputs, torch, dev):
+    """sphere3d_128 (3-D Q1 128^3, one sphere R = 4, eps4 = 0.05, lambda = 3.19,
+    u0 = -0.55): two 10-step backward-Euler runs of dt = 0.2 from the same
+    state, FP64 V-cycle and FP32 V-cycle (FP64 residual, Arnoldi and norms in
+    both), with Newton/FGMRES counts and the difference of the FP32 run from the
+    FP64 run on the increments U^k - U^0."""
+    w = inputs.workload("sphere3d_128")
+    log(f"{w.name}: n={w.n} dof={w.n_dof}")
+    pb = binding.problem_for(w)
+    n = pb.n_dof
+    U0 = torch.from_numpy(inputs.initial_state_fast(w).reshape(-1)).to(dev)
+    steps = w.steps
+    runs = {}
+    for name, prec in (("fp64_gmg", binding.PF_FP64), ("fp32_gmg", binding.PF_FP32)):
+        opts = binding.default_opts(pc=binding.PF_PC_GMG, pc_precision=prec, jv_mode=binding.PF_JV_FD,
+                                    tau_r=1e-10)
+        S = torch.empty((steps + 1, n), dtype=torch.float64, device=dev)
+        S[0].copy_(U0)
+        recs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            S[k + 1].copy_(S[k])
+            recs.append(pb.pf_newton_step(S[k], S[k + 1], opts))
+        torch.cuda.synchronize()
+        runs[name] = (S, recs, 1e3 * (time.perf_counter() - t0) / steps)
+    S64, S32 = runs["fp64_gmg"][0], runs["fp32_gmg"][0]
+    per_step = [increment_difference(torch, S32[k] - U0, S64[k] - U0) for k in range(1, steps + 1)]
+    out = {"workload": f"{w.name}: 3-D Q1 {w.n}^3, sphere R={w.radius}, eps4={w.eps4}, "
+                       f"lambda={w.lam}, u0={w.u0}, D={w.D}, dt={w.dt}",
+           "unknowns": n, "steps": steps}
+    for name, (S, recs, ms) in runs.items():
+        out[name] = {"ms_per_step": round(ms, 2), "newton_its": [r["newton_its"] for r in recs],
+                     "gmres_its": [r["gmres_its_total"] for r in recs],
+                     "f_final_rel_max": max(r["f_final"] / r["f0"] for r in recs)}
+    out["fp32_vs_fp64_increment_rel_max"] = max(d["rel"] for d in per_step)
+    out["fp32_vs_fp64_increment_field_maxabs_max"] = [max(d["field_maxabs"][f] for d in per_step)
+                                                      for f in range(2)]
+    out["within_1e-8"] = (out["fp32_vs_fp64_increment_rel_max"] <= 1e-8
+                          and max(out["fp32_vs_fp64_increment_field_maxabs_max"]) <= 1e-8)
+    out["speedup_mixed"] = round(runs["fp64_gmg"][2] / runs["fp32_gmg"][2], 3)
+    del runs, S64, S32
+    pb.close()
+    log(f"{w.name} done")
+    return out
+
+
+def config4_leg(a, binding, inputs, torch, dev):
+    """adjoint2d_512 (2-D Q1 512^2, one seed R = 4, dt = 0.5, 20 steps): the
+    misfit of the final phase field against the run with eps4 = 0.03, its
+    gradient in (eps4, lambda) at (0.02, 1.6) through the autograd Functions
+    (checkpointed forward, discrete adjoint backward), and central differences
+    of the misfit with steps 1e-4 eps4 and 1e-4 lambda."""
+    from paper_2006_16764_amd import evolve
+    w = inputs.workload("adjoint2d_512")
+    log(f"{w.name}: n={w.n} dof={w.n_dof}")
+    pb = binding.problem_for(w)
+    U0 = torch.from_numpy(inputs.initial_state_fast(w).reshape(-1)).to(dev)
+    steps = w.steps
+    opts = binding.default_opts(pc=binding.PF_PC_GMG, pc_precision=binding.PF_FP64,
+                                jv_mode=binding.PF_JV_FD, tau_r=1e-12)
+    f64 = dict(dtype=torch.float64)
+    with torch.no_grad():
+        target = evolve.evolve(torch.tensor(0.03, **f64), torch.tensor(w.lam, **f64), U0, pb, steps,
+                               opts).view(-1, 2)[:, 0].contiguous()
+    e = torch.tensor(w.eps4, requires_grad=True, **f64)
+    lam = torch.tensor(w.lam, requires_grad=True, **f64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    UK = evolve.evolve(e, lam, U0, pb, steps, opts)
+    L = evolve.misfit(UK, target, pb)
+    Lv = float(L)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    grad = [float(e.grad), float(lam.grad)]
+
+    def misfit_at(ev, lv):
+        with torch.no_grad():
+            uk = evolve.evolve(torch.tensor(ev, **f64), torch.tensor(lv, **f64), U0, pb, steps, opts)
+            return float(evolve.misfit(uk, target, pb))
+
+    he, hl = 1e-4 * w.eps4, 1e-4 * w.lam
+    fd = [(misfit_at(w.eps4 + he, w.lam) - misfit_at(w.eps4 - he, w.lam)) / (2 * he),
+          (misfit_at(w.eps4, w.lam + hl) - misfit_at(w.eps4, w.lam - hl)) / (2 * hl)]
+    pb.close()
+    log(f"{w.name} done")
+    return {"workload": f"{w.name}: 2-D Q1 {w.n}^2, seed R={w.radius}, dt={w.dt}, {steps} steps, "
+                        f"eps4 {w.eps4} (target run 0.03), lambda {w.lam}",
+            "unknowns": 2 * w.n_nodes, "misfit": Lv,
+            "forward_ms": round(1e3 * t_fwd, 1), "backward_ms": round(1e3 * t_bwd, 1),
+            "grad_eps4_lambda": grad, "central_fd_eps4_lambda": fd,
+            "rel_diff_adjoint_vs_fd": [abs(g - f) / max(abs(f), 1e-300) for g, f in zip(grad, fd)]}
+
+
+def probe(a, binding, inputs, torch):
+    """The hot-path kernels a few times each on the workload, for profilers."""
+    only = set(a.probe_only.split(",")) if a.probe_only else None
+    w = inputs.workload(a.workload)
+    torch.cuda.set_device(0)
+    pb = binding.problem_for(w)
+    n = pb.n_dof
+    U0 = torch.from_numpy(inputs.initial_state_fast(w).reshape(-1)).cuda()
+    rng = np.random.default_rng(3)
+    U = U0 + torch.from_numpy(1e-3 * rng.standard_normal(n)).cuda()
+    v = torch.from_numpy(rng.standard_normal(n)).cuda()
+    out, out2 = pb.new_vector(), pb.new_vector()
+    F = pb.new_vector()
+    gp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def want(k):
+        return only is None or k in only
+
+    if want("copy"):
+        src = torch.empty(a.probe_copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy: {src.numel() * 8} bytes read, {src.numel() * 8} bytes written", flush=True)
+        del src, dst
+    pb.pf_residual(U, U0, F)
+    calls = [
+        ("residual", lambda: pb.pf_residual(U, U0, out)),
+        ("fd", lambda: pb.pf_jvp(U, U0, v, out, mode=binding.PF_JV_FD, F0=F)),
+        ("jvp", lambda: pb.pf_jvp(U, U0, v, out, mode=binding.PF_JV_ANALYTIC)),
+        ("vjp", lambda: pb.pf_vjp(U, U0, v, out, out2, gp)),
+        ("vjpp", lambda: pb.pf_vjp(U, U0, v, None, out2, gp)),
+        ("vjpu", lambda: pb.pf_vjp(U, U0, v, out, None, None)),
+    ]
+    for name, fn in calls:
+        if want(name) and (name not in ("vjpp", "vjpu") or only is not None):
+            for _ in range(a.probe_reps):
+                fn()
+            torch.cuda.synchronize()
+            print(f"{name}: {a.probe_reps} calls, nodes {w.n_nodes}, elements {w.n_elems}", flush=True)
+    for name, prec in (("pc32", binding.PF_FP32), ("pc64", binding.PF_FP64)):
+        if want(name):
+            pb.pf_precond_setup(U, binding.PF_PC_GMG, prec)
+            for _ in range(a.probe_reps):
+                pb.pf_precond_apply(v, out)
+            torch.cuda.synchronize()
+            print(f"{name}: {a.probe_reps} V-cycles", flush=True)
+    return 0 if pb.close() == 0 else 1
 
 
 def alloy_leg(a, binding, inputs, torch, dev, time_call, stream):
@@ -464,35 +762,165 @@ def freegrowth_leg(a, binding, inputs, torch, dev, time_call):
     return out
 
 
-def cpu_baseline(w, U, Uprev, v, seconds):
-    """Oracle analytic Jv (complex step) on z-slabs of the same state, 1 thread."""
+def _oracle_slab(kind, dim, n, half_width, U, Up, V, pdict, keep):
+    """Worker: the oracle's residual or complex-step Jv on one slab mesh, one
+    thread.  Returns (result or None, seconds)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import deriv, fem
+    from oracle.fem import Mesh, Params
+
+    with threadpool_limits(limits=1):
+        m = Mesh(dim, n, half_width)
+        p = Params(**pdict)
+        t = time.perf_counter()
+        if kind == "residual":
+            out = fem.residual(m, U, Up, p)
+        else:
+            out = deriv.jvp(m, U, Up, V, p)
+        dt = time.perf_counter() - t
+    return (out if keep else None), dt
+
+
+def _slabs(dim, n, layers):
+    """Element-layer ranges [z0, z1) along the last axis."""
+    return [(z0, min(n, z0 + layers)) for z0 in range(0, n, layers)]
+
+
+def _slab_args(dim, n, h, z0, z1):
+    nn_plane = (n + 1) ** (dim - 1)
+    sl = slice(z0 * nn_plane, (z1 + 1) * nn_plane)
+    ns = [n] * (dim - 1) + [z1 - z0]
+    hw = [n * h / 2] * (dim - 1) + [(z1 - z0) * h / 2]
+    return sl, ns, hw
+
+
+def oracle_residual_parallel(pool, dim, n, h, U, Up, pdict, layers):
+    """The oracle's residual F(U; Up) on an n^dim mesh of spacing h, assembled
+    from element slabs evaluated in parallel processes (the nodes shared by two
+    slabs receive both slabs' sums).  Returns (F, wall seconds, summed worker
+    seconds)."""
+    t0 = time.perf_counter()
+    futs = []
+    for z0, z1 in _slabs(dim, n, layers):
+        sl, ns, hw = _slab_args(dim, n, h, z0, z1)
+        futs.append((sl, pool.submit(_oracle_slab, "residual", dim, ns, hw, U[sl], Up[sl], None,
+                                     pdict, True)))
+    F = np.zeros_like(U)
+    busy = 0.0
+    for sl, f in futs:
+        Fs, dt = f.result()
+        F[sl] += Fs
+        busy += dt
+    return F, time.perf_counter() - t0, busy
+
+
+def certify_leg(pool, workers, w, Unew, Ustart, st):
+    """The oracle's own residual at the GPU's mixed-precision Newton solution of
+    the 256^3 step: |F_oracle(U_gpu; U^n)| against |F_oracle(U^n; U^n)| (the
+    Newton start) and tau_r = 1e-10."""
+    U = Unew.reshape(-1, 2)
+    Us = Ustart.reshape(-1, 2)
+    pdict = dict(dt=w.dt, eps4=w.eps4, lam=w.lam, D=w.D, delta2=w.delta2)
+    F1, t1, b1 = oracle_residual_parallel(pool, w.dim, w.n, w.h, U, Us, pdict, 8)
+    f1 = float(np.linalg.norm(F1))
+    del F1
+    F0, t0, b0 = oracle_residual_parallel(pool, w.dim, w.n, w.h, Us, Us, pdict, 8)
+    f0 = float(np.linalg.norm(F0))
+    del F0
+    return {"state": "mixed-precision Newton solution of the 256^3 step (FP32 V-cycle)",
+            "f_oracle": f1, "f0_oracle": f0, "ratio": f1 / f0, "tau_r": 1e-10,
+            "certified": f1 <= 1e-10 * f0,
+            "gpu_ratio": st["f_final"] / st["f0"],
+            "oracle_seconds": round(t0 + t1, 1), "oracle_cpu_seconds": round(b0 + b1, 1),
+            "workers": workers,
+            "oracle_residual_mdofs": round(2 * 2 * w.n_nodes / (t0 + t1) / 1e6, 3)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pool, workers, w, U, Uprev, v, seconds, certify):
+    """The oracle's analytic Jv (complex-step residual) on z-slabs of the same
+    state: one process with one thread, then `workers` processes of one thread
+    each (element-chunk process parallelism); the oracle's residual on the
+    seeds2d_1024 and sphere3d_128 meshes (all workers) beside the 256^3 one of
+    the certification."""
     from threadpoolctl import threadpool_limits
 
     from oracle import deriv
     from oracle.fem import Mesh, Params
+    from paper_2006_16764_amd import inputs
 
     nn = w.n + 1
-    U = U.reshape(nn, nn, nn, 2)
-    Up = Uprev.reshape(nn, nn, nn, 2)
-    V = v.reshape(nn, nn, nn, 2)
-    p = Params(dt=w.dt, eps4=w.eps4, lam=w.lam, D=w.D, delta2=w.delta2)
-    layers = 1
+    plane = nn * nn
+    pdict = dict(dt=w.dt, eps4=w.eps4, lam=w.lam, D=w.D, delta2=w.delta2)
+    U2, Up2, V2 = U.reshape(-1, 2), Uprev.reshape(-1, 2), v.reshape(-1, 2)
+    # one process, one thread: slabs of one element layer around the middle
     total_t, total_dof, slabs = 0.0, 0, 0
+    p = Params(**pdict)
     with threadpool_limits(limits=1):
         z0 = w.n // 2 - 1
-        while total_t < seconds and slabs < 64:
-            m = Mesh(3, [w.n, w.n, layers], [w.half_width, w.half_width, w.h * layers / 2])
-            sl = slice(z0, z0 + layers + 1)
+        while total_t < seconds / 2 and slabs < 32:
+            m = Mesh(3, [w.n, w.n, 1], [w.half_width, w.half_width, w.h / 2])
+            sl = slice(z0 * plane, (z0 + 2) * plane)
             t = time.perf_counter()
-            deriv.jvp(m, U[sl].reshape(-1, 2), Up[sl].reshape(-1, 2), V[sl].reshape(-1, 2), p)
+            deriv.jvp(m, U2[sl], Up2[sl], V2[sl], p)
             total_t += time.perf_counter() - t
             total_dof += 2 * m.n_nodes
             slabs += 1
-    return {"value": round(total_dof / total_t / 1e6, 4), "unit": "MDOF/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{slabs} x analytic Jv (complex-step residual) on a 256x256x{layers} element "
-                      f"slab of the same state, {total_t:.1f} s, BLAS limited to 1 thread; "
-                      f"host has {os.cpu_count()} logical CPUs"}
+    single = total_dof / total_t / 1e6
+    # all workers: one-layer slabs spread over the mesh, in rounds of `workers`
+    t0 = time.perf_counter()
+    done_dof, rounds = 0, 0
+    while time.perf_counter() - t0 < seconds / 2 and rounds < 8:
+        futs = []
+        for k in range(workers):
+            z = (k * 7 + rounds * 3) % (w.n - 1)
+            sl = slice(z * plane, (z + 2) * plane)
+            futs.append(pool.submit(_oracle_slab, "jvp", 3, [w.n, w.n, 1],
+                                    [w.half_width, w.half_width, w.h / 2], U2[sl], Up2[sl], V2[sl],
+                                    pdict, False))
+        for f in futs:
+            f.result()
+            done_dof += 2 * 2 * plane
+        rounds += 1
+    par_t = time.perf_counter() - t0
+    parallel = done_dof / par_t / 1e6
+    # the oracle's residual on the other meshes (all workers)
+    residual = {}
+    for name in ("seeds2d_1024", "sphere3d_128"):
+        wk = inputs.workload(name)
+        Uk = inputs.initial_state_fast(wk)
+        Upk = Uk.copy()
+        Uk = Uk + 1e-3 * np.random.default_rng(29).standard_normal(Uk.shape)
+        pk = dict(dt=wk.dt, eps4=wk.eps4, lam=wk.lam, D=wk.D, delta2=wk.delta2)
+        _, tw, tb = oracle_residual_parallel(pool, wk.dim, wk.n, wk.h, Uk, Upk, pk,
+                                             max(1, wk.n // (4 * workers)))
+        residual[name] = {"wall_s": round(tw, 2), "cpu_s": round(tb, 2),
+                          "mdofs": round(wk.n_dof / tw / 1e6, 3),
+                          "mdofs_one_core": round(wk.n_dof / tb / 1e6, 4)}
+    if certify is not None:
+        residual[w.name] = {"wall_s": round(certify["oracle_seconds"] / 2, 2),
+                            "cpu_s": round(certify["oracle_cpu_seconds"] / 2, 2),
+                            "mdofs": round(2 * w.n_dof / certify["oracle_seconds"] / 1e6, 3),
+                            "mdofs_one_core": round(2 * w.n_dof / certify["oracle_cpu_seconds"] / 1e6, 4)}
+    return {"value": round(parallel, 4), "unit": "MDOF/s", "cores": workers, "kind": "oracle",
+            "sample": f"analytic Jv (complex-step residual) of the oracle on {rounds * workers} "
+                      f"256x256x1 element slabs of the same state, {workers} processes of one "
+                      f"thread, {par_t:.1f} s; host: {_cpu_model()}, {os.cpu_count()} logical CPUs, "
+                      f"{len(os.sched_getaffinity(0))} usable",
+            "single_process": {"value": round(single, 4), "unit": "MDOF/s", "cores": 1,
+                               "sample": f"{slabs} slabs, {total_t:.1f} s, BLAS limited to 1 thread"},
+            "residual": residual}
 
 
 if __name__ == "__main__":
