@@ -177,9 +177,9 @@ int pf_residual(pf_problem* pb, const double* U, const double* Uprev, const doub
  * fixed array of 64 MiB inside the library, one copy per device, held from the
  * first call on that device until the process ends; its device address is
  * looked up on that first call.  Meshes whose scratch exceeds it -- beyond
- * about 853 tiles of 16^3 elements in 3-D (128^3 fits), or 2^20 elements in
- * 2-D (1024^2 fits) -- are rejected with PF_ERR_INVALID_ARG before anything is
- * launched.  All calls on one device share that array: calls that overlap in
+ * 2727 tiles of 16^3 elements in 3-D (128^3 and 192^3 fit, 256^3 does not),
+ * or 2^20 elements in 2-D (1024^2 fits) -- are rejected with
+ * PF_ERR_INVALID_ARG before anything is launched.  All calls on one device share that array: calls that overlap in
  * time on one device (other streams or threads) race and must not be issued.
  * The array holds the last call's partial sums; nothing in it needs clearing.
  * U, Uprev, F: device, 2*n_nodes doubles; F must not alias U or Uprev. */

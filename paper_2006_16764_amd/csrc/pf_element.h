@@ -123,14 +123,39 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // at the end of each row of points with the row's weight (y, z weights and
 // the Jacobian): point weight = w_x w_row.  Row sums are accumulated with the
 // x weights only and scaled once per row.
-template <int NG, int NV, int NS, int NP, class Phys>
-__device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
-                                     const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS > 0 ? NS : 1][8],
-                                     double (&op)[NP > 0 ? NP : 1][8], Phys& phys) {
+//
+// quad3g takes the corner values from load(gz, ng, nv), called at the start of
+// every Gauss plane gz: a loader that reads them from memory each time keeps
+// them out of registers between planes (quad3 passes register arrays).
+//
+// The element outputs are accumulated through acc: acc.s(o, a, v) adds v to
+// value-and-flux output o at corner a, acc.p(o, a, v) to value-only output o
+// (RegAcc: register arrays; StridedAcc: a lane's slots in memory).
+template <int NS, int NP>
+struct RegAcc {
+  double (&os)[NS > 0 ? NS : 1][8];
+  double (&op)[NP > 0 ? NP : 1][8];
+  __device__ __forceinline__ void s(int o, int a, double v) { os[o][a] += v; }
+  __device__ __forceinline__ void p(int o, int a, double v) { op[o][a] += v; }
+};
+// Output o, corner a at base_s[(o * 8 + a) * stride] (value-only outputs at
+// base_p likewise).
+struct StridedAcc {
+  double* base_s;
+  double* base_p;
+  int stride;
+  __device__ __forceinline__ void s(int o, int a, double v) { base_s[(o * 8 + a) * stride] += v; }
+  __device__ __forceinline__ void p(int o, int a, double v) { base_p[(o * 8 + a) * stride] += v; }
+};
+
+template <int NG, int NV, int NS, int NP, class Phys, class Load, class Acc>
+__device__ __forceinline__ void quad3g(const Geo& G, Load& load, Acc& acc, Phys& phys) {
   const double ihx = G.ih[0], ihy = G.ih[1], ihz = G.ih[2];
 #pragma unroll 1
   for (int gz = 0; gz < 3; ++gz) {
     const double bz0 = Q1::b0(gz), bz1 = Q1::b1(gz);
+    double ng[NG][8], nv[NV > 0 ? NV : 1][8];
+    load(gz, ng, nv);
     double pg[NG][4], dz[NG][4], pv[NV > 0 ? NV : 1][4];
     // b0 + b1 = 1: value = q0 + b1 (q1 - q0), and the difference also gives
     // the derivative along the axis
@@ -263,16 +288,33 @@ PF_UNROLL(PF_GY_UNROLL)
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
-        os[o][a] += bz0 * S[o][a] - Zc[o][a] * ihz;
-        os[o][a + 4] += bz1 * S[o][a] + Zc[o][a] * ihz;
+        acc.s(o, a, bz0 * S[o][a] - Zc[o][a] * ihz);
+        acc.s(o, a + 4, bz1 * S[o][a] + Zc[o][a] * ihz);
       }
 #pragma unroll
       for (int o = 0; o < NP; ++o) {
-        op[o][a] += bz0 * P[o][a];
-        op[o][a + 4] += bz1 * P[o][a];
+        acc.p(o, a, bz0 * P[o][a]);
+        acc.p(o, a + 4, bz1 * P[o][a]);
       }
     }
   }
+}
+
+template <int NG, int NV, int NS, int NP, class Phys>
+__device__ __forceinline__ void quad3(const Geo& G, const double (&ng)[NG][8],
+                                     const double (&nv)[NV > 0 ? NV : 1][8], double (&os)[NS > 0 ? NS : 1][8],
+                                     double (&op)[NP > 0 ? NP : 1][8], Phys& phys) {
+  auto load = [&](int, double (&g)[NG][8], double (&v)[NV > 0 ? NV : 1][8]) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+#pragma unroll
+      for (int f = 0; f < NG; ++f) g[f][a] = ng[f][a];
+#pragma unroll
+      for (int f = 0; f < (NV > 0 ? NV : 1); ++f) v[f][a] = nv[f][a];
+    }
+  };
+  RegAcc<NS, NP> acc{os, op};
+  quad3g<NG, NV, NS, NP>(G, load, acc, phys);
 }
 
 // ----------------------------------------------------------------- Gauss-rule part, 2-D
@@ -373,9 +415,10 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
 template <int DIM>
 struct Aniso {
   // primal quantities kept for the tangent: q = |g|^2, S = sum g^4, iQ = 1/Q,
-  // iQ2 = 1/Q^2, a, a^2, aqc = a q 16 eps4/Q^2, SQ = S/Q, g2_k = g_k^2 and
-  // t_k with J_k = g_k t_k, t_k = a^2 + aqc (g_k^2 - S/Q).
-  double q, S, iQ, iQ2, a, a2, aqc, SQ, g2[3], t[3], J[3];
+  // iQ2 = 1/Q^2, a, a^2, b = 16 eps4/Q^2, aqc = a q b, SQ = S/Q, g2_k = g_k^2,
+  // gm_k = g_k^2 - S/Q and t_k with J_k = g_k t_k, t_k = a^2 + aqc gm_k
+  // (da/dg_k = b g_k gm_k).
+  double q, S, iQ, iQ2, a, a2, b, aqc, SQ, g2[3], gm[3], t[3], J[3];
   __device__ __forceinline__ void flux(const double* g, const Geo& G) {
     q = 0.0;
     S = 0.0;
@@ -390,44 +433,46 @@ struct Aniso {
     a = fma(G.e4x4 * S, iQ2, G.a0);
     SQ = S * iQ;
     a2 = a * a;
-    aqc = a * q * (G.e16 * iQ2);
+    b = G.e16 * iQ2;
+    aqc = (a * q) * b;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      t[k] = fma(aqc, g2[k] - SQ, a2);
+      gm[k] = g2[k] - SQ;
+      t[k] = fma(aqc, gm[k], a2);
       J[k] = g[k] * t[k];
     }
   }
   // da/dg_k = 16 eps4 g_k (g_k^2 - S/Q)/Q^2 (after flux())
-  __device__ __forceinline__ double dadg(const double* g, int k, const Geo& G) const {
-    return G.e16 * iQ2 * g[k] * (g2[k] - SQ);
+  __device__ __forceinline__ double dadg(const double* g, int k, const Geo&) const {
+    return b * (g[k] * gm[k]);
   }
   // Directional derivative along v (after flux()): Hv = (dJ/dg) v, the Hessian
   // of a^2 |g|^2 / 2 times v (symmetric), and da = (da/dg) . v.  Forward-mode
-  // differentiation of flux():
-  //   dq = 2 g.v, dS = 4 sum g^3 v, d(1/Q) = -dq/Q^2, d(1/Q^2) = -2 dq/Q^3,
-  //   da = 4 eps4 (dS/Q^2 + S d(1/Q^2)), d(a^2) = 2 a da,
-  //   d(aqc) = 16 eps4 (da q/Q^2 + a dq/Q^2 + a q d(1/Q^2)),
-  //   d(S/Q) = dS/Q + S d(1/Q),
-  //   dt_k = d(a^2) + d(aqc) (g_k^2 - S/Q) + aqc (2 g_k v_k - d(S/Q)),
+  // differentiation of flux(), with gv = g.v and g3v = sum g_k^3 v_k:
+  //   da = b (g3v - (S/Q) gv),  d(a^2) = 2 a da,  dq = 2 gv,
+  //   d(S/Q) = (4 g3v - (S/Q) dq)/Q,
+  //   d(aqc) = b (da q + a dq (1 - 2 q/Q))   (db = -2 b dq/Q),
+  //   dt_k = d(a^2) + d(aqc) gm_k + aqc (2 g_k v_k - d(S/Q)),
   //   (Hv)_k = v_k t_k + g_k dt_k.
-  __device__ __forceinline__ void hvp(const double* g, const double* v, const Geo& G, double* Hv,
+  __device__ __forceinline__ void hvp(const double* g, const double* v, const Geo&, double* Hv,
                                       double& da) const {
     double gv = 0.0, g3v = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      gv = fma(g[k], v[k], gv);
-      g3v = fma(g2[k] * g[k], v[k], g3v);
+      const double gvk = g[k] * v[k];
+      gv += gvk;
+      g3v = fma(g2[k], gvk, g3v);
     }
-    const double dq = 2.0 * gv, dS = 4.0 * g3v;
-    const double diQ = -iQ2 * dq;
-    const double diQ2 = 2.0 * iQ * diQ;
-    da = G.e4x4 * fma(dS, iQ2, S * diQ2);
-    const double da2 = 2.0 * a * da;
-    const double daqc = G.e16 * fma(da * q, iQ2, a * fma(dq, iQ2, q * diQ2));
-    const double dSQ = fma(dS, iQ, S * diQ);
+    da = b * fma(-SQ, gv, g3v);
+    const double dq = gv + gv;
+    const double da2 = (a + a) * da;
+    const double dSQ = iQ * fma(4.0, g3v, -SQ * dq);
+    const double daqc = b * fma(da, q, (a * dq) * fma(-2.0 * q, iQ, 1.0));
+    const double K = fma(-aqc, dSQ, da2);
+    const double aqc2 = aqc + aqc;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double dt = fma(daqc, g2[k] - SQ, fma(aqc, fma(2.0 * g[k], v[k], -dSQ), da2));
+      const double dt = fma(daqc, gm[k], fma(aqc2 * g[k], v[k], K));
       Hv[k] = fma(v[k], t[k], g[k] * dt);
     }
   }
@@ -535,16 +580,20 @@ struct PhysVjp {
     s[0] = w1 * (A.a2 * G.idtm - Rp);
     p[0] = w1 * G.lam * om * om;
     p[1] = -w1 * A.a2 * G.idtm;
-    // parameter derivatives: da/deps4 = -3 + 4 S/Q^2, d(da/dg)/deps4 = (da/dg)/eps4
+    // parameter derivatives: da/deps4 = -3 + 4 S/Q^2; d(da/dg_k)/deps4 = dae_k = 16 g_k gm_k/Q^2, and
+    // da/dg_k = eps4 dae_k; J_k = a^2 g_k + a q da/dg_k, so
+    // dJ_k/deps4 = 2 a ae g_k + ae q da/dg_k + a q dae_k
     const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
+    const double c16 = 16.0 * A.iQ2, tae = 2.0 * A.a * ae, aeq = ae * A.q, aq = A.a * A.q;
     double Je_w = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const double gk = gg[0][k];
-      const double dae = 16.0 * A.iQ2 * gk * (A.g2[k] - A.SQ);
-      const double dak = G.eps4 * dae;
-      const double Je = 2.0 * A.a * ae * gk + ae * A.q * dak + A.a * A.q * dae;
-      Je_w += Je * gg[1][k];
+      const double ggm = gk * A.gm[k];
+      const double dae = c16 * ggm;
+      const double dak = A.b * ggm;
+      const double Je = fma(tae, gk, fma(aeq, dak, aq * dae));
+      Je_w = fma(Je, gg[1][k], Je_w);
       f[0][k] = Hw[k] + m * dak;
     }
 #pragma unroll
@@ -580,7 +629,7 @@ struct PhysVjpU {
     s[0] = w1 * (A.a2 * G.idtm - Rp);
     p[0] = w1 * G.lam * om * om;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m, A.dadg(gg[0], k, G), Hw[k]) : 0.0;
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m * A.b, gg[0][k] * A.gm[k], Hw[k]) : 0.0;
   }
 };
 
@@ -616,15 +665,20 @@ struct PhysVjpPrev {
     const double om = 1.0 - phi * phi;
     const double m = 2.0 * A.a * dphi * G.idtm * w1;
     p[0] = -w1 * A.a2 * G.idtm;
+    // da/deps4 = -3 + 4 S/Q^2; d(da/dg_k)/deps4 = dae_k = 16 g_k gm_k/Q^2, and
+    // da/dg_k = eps4 dae_k; J_k = a^2 g_k + a q da/dg_k, so
+    // dJ_k/deps4 = 2 a ae g_k + ae q da/dg_k + a q dae_k
     const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
+    const double c16 = 16.0 * A.iQ2, tae = 2.0 * A.a * ae, aeq = ae * A.q, aq = A.a * A.q;
     double Je_w = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
       const double gk = gg[0][k];
-      const double dae = 16.0 * A.iQ2 * gk * (A.g2[k] - A.SQ);
-      const double dak = G.eps4 * dae;
-      const double Je = 2.0 * A.a * ae * gk + ae * A.q * dak + A.a * A.q * dae;
-      Je_w += Je * gg[1][k];
+      const double ggm = gk * A.gm[k];
+      const double dae = c16 * ggm;
+      const double dak = A.b * ggm;
+      const double Je = fma(tae, gk, fma(aeq, dak, aq * dae));
+      Je_w = fma(Je, gg[1][k], Je_w);
     }
     pe = m * ae + Je_w;
     pl = w1 * om * om * u;
@@ -654,6 +708,154 @@ struct Element {
                                              const double (&xk)[NA], double ck, double (&y)[NA]) {
     if constexpr (DIM == 3) mass_stiff3(G, xm, cm, xk, ck, y);
     else mass_stiff2(G, xm, cm, xk, ck, y);
+  }
+
+  // The tangent and adjoint modes (3-D) with corner values read on demand:
+  // src.plane(gz) is called before Gauss plane gz's corner reads and
+  // src.loaded(gz) after them; src.corner(a, u, p, v) gives the (phi, u)
+  // pairs of the state, the previous state and the direction/cotangent at
+  // corner a.  The linear part re-reads the direction after the Gauss rule, so
+  // no corner value is held in registers across planes.  The element vector
+  // is left in memory: output field o at corner a in src.out(o)[a *
+  // src.stride()].  The analytic product and the transposed product
+  // accumulate their Gauss-rule outputs there directly (no register
+  // accumulators); the others accumulate in registers and store at the end.
+  template <class Src>
+  __device__ __forceinline__ static void run_src(const Geo& G, Src& src, double& ge, double& gl) {
+    static_assert(DIM == 3 && MODE != MODE_RES && MODE != MODE_FD, "tangent and adjoint modes only");
+    const int T = src.stride();
+    if constexpr (MODE == MODE_JVP) {
+      auto load = [&](int gz, double (&ng)[2][NA], double (&nv)[3][NA]) {
+        src.plane(gz);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          double2 u, p, v;
+          src.corner(a, u, p, v);
+          ng[0][a] = u.x;
+          ng[1][a] = v.x;
+          nv[0][a] = u.y;
+          nv[1][a] = u.x - p.x;
+          nv[2][a] = v.y;
+        }
+        src.loaded(gz);
+      };
+      double* o0 = src.out(0);
+      double* o1 = src.out(1);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) o0[a * T] = 0.0;
+      StridedAcc acc{o0, nullptr, T};
+      PhysJvp<DIM> ph(G);
+      quad3g<2, 3, 1, 0>(G, load, acc, ph);
+      // d F2 = M (v_u - theta v_phi/2)/dt + theta D K v_u
+      double y[NA], v1[NA], f2[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        double2 u, p, v;
+        src.corner(a, u, p, v);
+        v1[a] = v.y;
+        y[a] = v.y - G.hth * v.x;
+        f2[a] = 0.0;
+        o0[a * T] = G.theta * o0[a * T];
+      }
+      lin(G, y, G.idt, v1, G.Dth, f2);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) o1[a * T] = f2[a];
+    } else {
+      // adjoint modes: gradient fields {phi, w1}, value fields {u, phi - phi^n}
+      auto load = [&](int gz, double (&ng)[2][NA], double (&nv)[2][NA]) {
+        src.plane(gz);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          double2 u, p, v;
+          src.corner(a, u, p, v);
+          ng[0][a] = u.x;
+          ng[1][a] = v.x;
+          nv[0][a] = u.y;
+          nv[1][a] = u.x - p.x;
+        }
+        src.loaded(gz);
+      };
+      double zero[NA], w2[NA];
+      if constexpr (MODE == MODE_VJPU) {
+        double* o0 = src.out(0);
+        double* o1 = src.out(1);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) o0[a * T] = o1[a * T] = 0.0;
+        StridedAcc acc{o0, o1, T};
+        PhysVjpU<DIM> ph(G);
+        quad3g<2, 2, 1, 1>(G, load, acc, ph);
+        // F2 part: gU_phi -= theta M w2/(2dt), gU_u += M w2/dt + theta D K w2
+        double y[NA], f0[NA], f1[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          double2 u, p, v;
+          src.corner(a, u, p, v);
+          w2[a] = v.y;
+          y[a] = G.idt * v.y;
+          zero[a] = 0.0;
+          f0[a] = G.theta * o0[a * T];
+          f1[a] = G.theta * o1[a * T];
+        }
+        lin(G, y, 1.0, w2, G.Dth, f1);
+        lin(G, y, -G.hth, zero, 0.0, f0);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          o0[a * T] = f0[a];
+          o1[a * T] = f1[a];
+        }
+      } else if constexpr (MODE == MODE_VJPP) {
+        double os[1][NA], op[1][NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) op[0][a] = 0.0;
+        RegAcc<0, 1> acc{os, op};
+        PhysVjpPrev<DIM> ph(G);
+        quad3g<2, 2, 0, 1>(G, load, acc, ph);
+        double mw[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          double2 u, p, v;
+          src.corner(a, u, p, v);
+          w2[a] = v.y;
+          zero[a] = mw[a] = 0.0;
+        }
+        lin(G, w2, 1.0, zero, 0.0, mw);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          src.out(0)[a * T] = G.theta * op[0][a] + G.hth * G.idt * mw[a];
+          src.out(1)[a * T] = -G.idt * mw[a];
+        }
+        ge = G.theta * ph.ge;
+        gl = G.theta * ph.gl;
+      } else {
+        double os[1][NA], op[2][NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) os[0][a] = op[0][a] = op[1][a] = 0.0;
+        RegAcc<1, 2> acc{os, op};
+        PhysVjp<DIM> ph(G);
+        quad3g<2, 2, 1, 2>(G, load, acc, ph);
+        // F2 part (M, K symmetric): gU_phi -= theta M w2/(2dt), gU_u += M w2/dt +
+        // theta D K w2, gUprev_phi += theta M w2/(2dt), gUprev_u -= M w2/dt
+        double mw[NA], kw[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          double2 u, p, v;
+          src.corner(a, u, p, v);
+          w2[a] = v.y;
+          zero[a] = mw[a] = kw[a] = 0.0;
+        }
+        lin(G, w2, 1.0, zero, 0.0, mw);
+        lin(G, zero, 0.0, w2, G.Dth, kw);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          src.out(0)[a * T] = G.theta * os[0][a] - G.hth * G.idt * mw[a];
+          src.out(1)[a * T] = G.theta * op[0][a] + G.idt * mw[a] + kw[a];
+          src.out(2)[a * T] = G.theta * op[1][a] + G.hth * G.idt * mw[a];
+          src.out(3)[a * T] = -G.idt * mw[a];
+        }
+        ge = G.theta * ph.ge;
+        gl = G.theta * ph.gl;
+      }
+    }
   }
 
   __device__ __forceinline__ static void run(const Geo& G, const double (&u0)[NA],

@@ -20,8 +20,10 @@
 // p(d) = sum_k [d_k != 0] 2^k.  The shared-cell sums come from the 8 (4)
 // cells around the node by partial sums along each axis; cells outside the
 // mesh count as zero, which gives the natural-boundary rows.  The diagonal is
-// the d = 0 weight, so no diagonal array is stored.  Both blocks are processed
-// by the same thread and stored as interleaved (phi, u) pairs.
+// the d = 0 weight; the smoothers recompute it from the cells, except the
+// zero-start step, which reads the phi-block diagonal stored per node at
+// set-up (the u-block diagonal is a product of cell counts).  Both blocks are
+// processed by the same thread and stored as interleaved (phi, u) pairs.
 #include <cmath>
 #include <cstdlib>
 #include <vector>

@@ -17,7 +17,7 @@ namespace pf {
 
 namespace {
 
-// 64 MiB: 853 tiles of 16^3 elements (128^3 fits) or 2^20 elements in 2-D.
+// 64 MiB: 2727 tiles of 16^3 elements (192^3 fits) or 2^20 elements in 2-D.
 constexpr long long kScratchBytes = 64LL << 20;
 constexpr long long kScratchDoubles = kScratchBytes / (long long)sizeof(double);
 
@@ -73,7 +73,7 @@ extern "C" int pf_residual_noalloc(const pf_params* params, const double* U, con
   if (need > kScratchDoubles) {
     set_error("pf_residual_noalloc: mesh needs " + std::to_string(need * 8) +
               " bytes of scratch, more than the fixed " + std::to_string(kScratchBytes) +
-              " (3-D: at most 853 tiles of 16^3 elements; 2-D: at most 2^20 elements)");
+              " (3-D: at most 2727 tiles of 16^3 elements; 2-D: at most 2^20 elements)");
     return PF_ERR_INVALID_ARG;
   }
   double* scr = nullptr;

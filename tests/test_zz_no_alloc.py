@@ -25,7 +25,9 @@ from paper_2006_16764_amd import inputs  # noqa: E402
 from parity import check  # noqa: E402
 
 SCRATCH_DOUBLES = (64 << 20) // 8
-TILE_DOUBLES = 17 * 17 * 17 * 2  # (16 + 1) node planes x 17 x 17 nodes x (phi, u)
+# side-buffer doubles per 16^3 tile: first and last node planes (17 x 17 nodes)
+# and the 64-node perimeter of the 15 planes between them, x (phi, u)
+TILE_DOUBLES = (2 * 17 * 17 + 15 * 64) * 2
 
 
 def note(msg):
@@ -78,8 +80,8 @@ def test_noalloc_equals_pf_residual_two_calls(meshes):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n", [(128, 128, 128), (16 * 853, 16, 16), (1024, 1024)],
-                         ids=["128^3", "853-tiles", "1024^2"])
+@pytest.mark.parametrize("n", [(128, 128, 128), (16 * 101, 16 * 27, 16), (1024, 1024)],
+                         ids=["128^3", "2727-tiles", "1024^2"])
 def test_noalloc_at_the_largest_sizes(n):
     note(f"pf_residual_noalloc largest size {n}")
     Fa, Fh, _, _ = run_pair(n, 3)
@@ -92,10 +94,10 @@ def test_noalloc_rejects_meshes_beyond_the_scratch():
     """Host-side rejection: nothing is dereferenced or launched (no GPU needed)."""
     from paper_2006_16764_amd import binding
     lib = binding.load()
-    assert (853 * TILE_DOUBLES <= SCRATCH_DOUBLES < 854 * TILE_DOUBLES)
+    assert (2727 * TILE_DOUBLES <= SCRATCH_DOUBLES < 2728 * TILE_DOUBLES)
     assert 2 * 4 * (1 << 20) == SCRATCH_DOUBLES
     fake = [ctypes.c_void_p(0x10000 + 0x1000 * k) for k in range(3)]
-    for n in [(16 * 854, 16, 16), (256, 256, 224), (1025, 1024), (4096, 300)]:
+    for n in [(16 * 2728, 16, 16), (256, 256, 224), (256, 256, 256), (1025, 1024), (4096, 300)]:
         p = params_for(n)
         rc = lib.pf_residual_noalloc(ctypes.byref(p), fake[0], fake[1], fake[2], None)
         assert rc == binding.PF_ERR_INVALID_ARG, n
