@@ -90,49 +90,54 @@ def flops_per_element(dim):
     matrices; Gauss part for the phi equation with phi interpolated with its
     gradient, u and (phi - phi^n)/(theta dt) as values, one output with value
     and flux parts, point sums taken with the x weights only and scaled per
-    row.  Pointwise physics 52 flops in 3-D (40 in 2-D) including a reciprocal
-    with two Newton steps and the a^2 accumulation for the preconditioner
-    coefficient.  Interpolation uses q0 + b1 (q1 - q0), so each point costs one
-    FMA per interpolated value.
+    row.  Pointwise physics 50 flops in 3-D including a reciprocal with two
+    Newton steps; the 3-D residual that also forms the cell mean of a^2 for the
+    preconditioner is a separate kernel with one more FMA per point and per
+    row.  The 2-D kernel always forms that mean: physics 40 flops, row weights
+    4.  Interpolation uses q0 + b1 (q1 - q0), so each point costs one FMA per
+    interpolated value.
     3-D: corner differences and scalings 48 + linear part 264 + 3 planes x
     (interpolation 40 + contraction 32) + 9 rows x (interpolation 26 + x
-    differences 6 + weights 5 + contraction 30) + 27 points x (interpolation 10
-    + physics 52 + contraction 14) = 3183.
+    differences 6 + weights 3 + contraction 30) + 27 points x (interpolation 10
+    + physics 50 + contraction 14) = 3111.
     2-D: corner differences and scalings 24 + linear part 88 + 3 rows x
     (interpolation 20 + x differences 5 + weights 4 + contraction 22) + 9 points
     x (interpolation 8 + physics 40 + contraction 10) = 787.
     The scalings include the time weight theta applied to the element vector.
     """
     if dim == 3:
-        return 48 + 264 + 3 * (40 + 32) + 9 * (26 + 6 + 5 + 30) + 27 * (10 + 52 + 14)
+        return 48 + 264 + 3 * (40 + 32) + 9 * (26 + 6 + 3 + 30) + 27 * (10 + 50 + 14)
     return 24 + 88 + 3 * (20 + 5 + 4 + 22) + 9 * (8 + 40 + 10)
 
 
 # FP64 flops per element counted for the roofline.  3-D: the counter value
-# (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 of k_fused3<0>, x 64 lanes / 256^3
-# elements), 3144 -- 39 below the source-level count of flops_per_element(3)
+# (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 of k_fused3<0, false>, x 64 lanes / 256^3
+# elements), 3072 -- 39 below the source-level count of flops_per_element(3)
 # because the compiler folds the constant point weights of the unrolled rows;
 # the executed count is the conservative one.  2-D: the source-level count.
-FLOPS_PER_ELEM = {3: 3144, 2: flops_per_element(2)}
+FLOPS_PER_ELEM = {3: 3072, 2: flops_per_element(2)}
 # The same counter for every 3-D element kernel of the residual family
-# (k_fused3<0..3>: residual, FD Jv, analytic Jv, VJP with all outputs), for the
-# per-kernel FP64 rates reported beside the roofline.
-KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3144, "fd_jv": 3110, "analytic_jv": 5109, "vjp": 6878}
+# (k_fused3<0..5>: residual, FD Jv, analytic Jv, VJP with all outputs, the
+# transposed-operator product alone, the previous-state and parameter product),
+# for the per-kernel FP64 rates reported beside the roofline.
+KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3072, "fd_jv": 3110, "analytic_jv": 5224, "vjp": 6993,
+                            "vjp_gU_only": 5571, "vjp_prev_and_params": 3634}
 BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
-# HBM bytes moved by one pf_residual call (k_fused3<0> + k_fixup3<0>) on the
-# 256^3 workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --probe`, each scaled by what the same counter
-# reads for a plain 1 GiB device copy (FETCH_SIZE reads half the bytes
-# fetched: x2; WRITE_SIZE is exact: x1).  Valid only for the kernel sources
-# whose digest is recorded; reported as null once they change (the figure is
-# then re-measured, never re-pointed at new sources).
+# HBM bytes moved by one pf_residual call (k_fused3<0, false> + k_fixup3<0>) on
+# the 256^3 workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# `bench.py --probe`, each scaled by what the same counter reads for a plain
+# 1 GiB device copy (FETCH_SIZE reads half the bytes fetched: x2; WRITE_SIZE
+# is exact: x1).  Valid only for the kernel sources whose digest is recorded;
+# reported as null once they change (the figure is then measured again, never
+# carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1428670704,
-    "sources_sha256": "de54692fbfb1654b01f9bef68465df7a6809097c16d09ac927ea65d2e24fd03a",
+    "bytes": 1106307896,
+    "sources_sha256": "a1e7710951b783f3004b23519710bcacd101e39d564f231d374e32c238faedbb",
 }
-TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h")
+TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
+                   "paper_2006_16764_amd/csrc/pf_internal.h")
 
 
 def sources_digest():
@@ -562,7 +567,8 @@ def config4_leg(a, binding, inputs, torch, dev):
     misfit of the final phase field against the run with eps4 = 0.03, its
     gradient in (eps4, lambda) at (0.02, 1.6) through the autograd Functions
     (checkpointed forward, discrete adjoint backward), and central differences
-    of the misfit with steps 1e-4 eps4 and 1e-4 lambda."""
+    of the misfit with steps h = 1e-4 eps4 and 1e-4 lambda, with h/2, and
+    their Richardson extrapolation."""
     from paper_2006_16764_amd import evolve
     w = inputs.workload("adjoint2d_512")
     log(f"{w.name}: n={w.n} dof={w.n_dof}")
@@ -594,9 +600,15 @@ def config4_leg(a, binding, inputs, torch, dev):
             uk = evolve.evolve(torch.tensor(ev, **f64), torch.tensor(lv, **f64), U0, pb, steps, opts)
             return float(evolve.misfit(uk, target, pb))
 
-    he, hl = 1e-4 * w.eps4, 1e-4 * w.lam
-    fd = [(misfit_at(w.eps4 + he, w.lam) - misfit_at(w.eps4 - he, w.lam)) / (2 * he),
-          (misfit_at(w.eps4, w.lam + hl) - misfit_at(w.eps4, w.lam - hl)) / (2 * hl)]
+    def central(he, hl):
+        return [(misfit_at(w.eps4 + he, w.lam) - misfit_at(w.eps4 - he, w.lam)) / (2 * he),
+                (misfit_at(w.eps4, w.lam + hl) - misfit_at(w.eps4, w.lam - hl)) / (2 * hl)]
+
+    # central differences with steps h and h/2, and their Richardson extrapolation
+    # (4 D(h/2) - D(h))/3, which removes the O(h^2) truncation term
+    fd = central(1e-4 * w.eps4, 1e-4 * w.lam)
+    fd2 = central(0.5e-4 * w.eps4, 0.5e-4 * w.lam)
+    fdr = [(4.0 * b - a) / 3.0 for a, b in zip(fd, fd2)]
     pb.close()
     log(f"{w.name} done")
     return {"workload": f"{w.name}: 2-D Q1 {w.n}^2, seed R={w.radius}, dt={w.dt}, {steps} steps, "
@@ -604,7 +616,10 @@ def config4_leg(a, binding, inputs, torch, dev):
             "unknowns": 2 * w.n_nodes, "misfit": Lv,
             "forward_ms": round(1e3 * t_fwd, 1), "backward_ms": round(1e3 * t_bwd, 1),
             "grad_eps4_lambda": grad, "central_fd_eps4_lambda": fd,
-            "rel_diff_adjoint_vs_fd": [abs(g - f) / max(abs(f), 1e-300) for g, f in zip(grad, fd)]}
+            "central_fd_half_step": fd2, "richardson_fd": fdr,
+            "rel_diff_adjoint_vs_fd": [abs(g - f) / max(abs(f), 1e-300) for g, f in zip(grad, fd)],
+            "rel_diff_adjoint_vs_fd_half_step": [abs(g - f) / max(abs(f), 1e-300) for g, f in zip(grad, fd2)],
+            "rel_diff_adjoint_vs_richardson": [abs(g - f) / max(abs(f), 1e-300) for g, f in zip(grad, fdr)]}
 
 
 def probe(a, binding, inputs, torch):

@@ -22,9 +22,12 @@ def test_vcycle_bytes_by_hand():
 
 
 def test_flop_counts():
-    assert bench.flops_per_element(3) == 3183
-    assert bench.FLOPS_PER_ELEM[3] == bench.KERNEL_FLOPS_PER_ELEM_3D["residual"] == 3144
-    assert bench.FLOPS_PER_ELEM[2] == bench.flops_per_element(2)
+    # source-level count of the plain 3-D residual (no preconditioner
+    # coefficient); the counter value of the compiled kernel is 39 below it
+    assert bench.flops_per_element(3) == 3111
+    assert bench.FLOPS_PER_ELEM[3] == bench.KERNEL_FLOPS_PER_ELEM_3D["residual"] == 3072
+    assert bench.flops_per_element(3) - bench.FLOPS_PER_ELEM[3] == 39
+    assert bench.FLOPS_PER_ELEM[2] == bench.flops_per_element(2) == 787
 
 
 def test_traffic_figure_is_tied_to_the_sources():
