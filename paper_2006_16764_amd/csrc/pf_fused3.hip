@@ -320,6 +320,17 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd<MODE>)
     const bool ring = lx == 0 || lx == lxmax || ly == 0 || ly == lymax || lz == 0 || lz == kzmax;
     if (ring) {
       double* s = side + (tile_base + side_slot(lx, ly, lz, lxmax, lymax, kzmax)) * NO;
+      if (MODE == MODE_FD) {
+        // the tile that owns the node in the fixup (below its upper extent
+        // along every axis, or on the mesh's upper face) subtracts F0 from its
+        // partial, so that the fixup needs no F0: Jv = (sum of partials)/eps
+        const bool owned = (lx < lxmax || tx == T.ntx - 1) && (ly < lymax || ty == T.nty - 1) &&
+                           (lz < kzmax || tz == T.ntz - 1);
+        const double2 f0 = owned ? sf[kDma ? lz % 3 : lz & 1][n] : make_double2(0.0, 0.0);
+        s[0] = acc[0] - f0.x;
+        s[1] = acc[1] - f0.y;
+        return;
+      }
 #pragma unroll
       for (int o = 0; o < NO; ++o) s[o] = acc[o];
       return;
@@ -557,7 +568,7 @@ __device__ __forceinline__ int axis_tiles(int c, int w, int nt, int nmax, int* t
 // side-buffer slots enumerate its ring nodes (a superset of the owned ones).
 template <int MODE>
 __global__ void __launch_bounds__(256)
-    k_fixup3(Geo G, Tiles T, const double* __restrict__ side, const double2* __restrict__ F0,
+    k_fixup3(Geo G, Tiles T, const double* __restrict__ side,
              const double* __restrict__ eps_dev, double2* __restrict__ out0,
              double2* __restrict__ out1) {
   constexpr int NO = ModeInfo<MODE>::NO;
@@ -613,8 +624,8 @@ __global__ void __launch_bounds__(256)
         }
     const long long g = gnode(G, x, y, z);
     if (MODE == MODE_FD) {
-      const double2 f0 = F0[g];
-      out0[g] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
+      // the owning tile's partial already holds -F0 (k_fused3)
+      out0[g] = make_double2(acc[0] * ie, acc[1] * ie);
     } else {
       if (out0) out0[g] = make_double2(acc[0], acc[1]);
       if (NO == 4 && out1) out1[g] = make_double2(acc[2 % NO], acc[3 % NO]);
@@ -652,7 +663,7 @@ int launch_mode(const Geo& G, double* side, const double* U, const double* Uprev
                        d2(Uprev), d2(v), eps_dev, d2(F0), reinterpret_cast<double2*>(out0),
                        reinterpret_cast<double2*>(out1), side, vjp_part, nullptr);
   PF_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nt), dim3(256), 0, s, G, T, side, d2(F0),
+  hipLaunchKernelGGL((k_fixup3<MODE>), dim3(nt), dim3(256), 0, s, G, T, side,
                      eps_dev, reinterpret_cast<double2*>(out0), reinterpret_cast<double2*>(out1));
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;

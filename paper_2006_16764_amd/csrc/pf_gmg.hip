@@ -36,6 +36,11 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kCoarseMin = 4;
+// 3-D restriction through LDS-staged fine planes (0: one thread per coarse
+// node gathering its 27 fine neighbours)
+#ifndef PF_RESTRICT_TILED
+#define PF_RESTRICT_TILED 1
+#endif
 constexpr int kCoarseDegree = 16;
 constexpr double kChebRatio = 4.0;
 constexpr double kChebSafety = 1.1;
@@ -497,6 +502,80 @@ __global__ void __launch_bounds__(kT)
   bc[I] = o;
 }
 
+// The same restriction on 3-D levels by coarse tiles: a workgroup owns RCX x
+// RCY coarse node columns and a chunk of kz coarse planes.  Each fine plane of
+// the tile's footprint ((2 RCX + 1) x (2 RCY + 1) fine nodes, zero outside the
+// mesh) is staged in LDS once and restricted along x and y there (weights 1/2,
+// 1, 1/2); coarse plane Z then combines the fine planes 2Z - 1, 2Z, 2Z + 1
+// with the z weights, the plane 2Z + 1 being carried to Z + 1.  Fine rows are
+// read once, coalesced, instead of by up to 8 coarse threads each.
+constexpr int RCX = 32, RCY = 8;
+
+template <class T>
+__global__ void __launch_bounds__(RCX * RCY)
+    k_restrict3t(LvK fg, LvK cg, const typename V2<T>::type* __restrict__ rf,
+                 typename V2<T>::type* __restrict__ bc, int kz) {
+  using T2 = typename V2<T>::type;
+  constexpr int FX = 2 * RCX + 1, FY = 2 * RCY + 1;
+  __shared__ T2 fs[FY][FX];
+  const int tid = threadIdx.x;
+  const int cx = tid % RCX, cy = tid / RCX;
+  const int ntx = (cg.nn[0] + RCX - 1) / RCX, nty = (cg.nn[1] + RCY - 1) / RCY;
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+  const int X0 = (tile % ntx) * RCX, Y0 = ((tile / ntx) % nty) * RCY;
+  const int Z0 = (tile / (ntx * nty)) * kz;
+  const int X = X0 + cx, Y = Y0 + cy;
+  const bool inside = X < cg.nn[0] && Y < cg.nn[1];
+  const int zend = min(Z0 + kz, cg.nn[2]);
+  const long long fplane = (long long)fg.nn[0] * fg.nn[1];
+  // x-y restriction of fine plane z at this thread's coarse column (0 for a
+  // plane outside the mesh)
+  auto plane = [&](int z) {
+    T2 p;
+    p.x = 0;
+    p.y = 0;
+    if (z < 0 || z >= fg.nn[2]) return p;
+    __syncthreads();  // the previous plane's reads are done
+    for (int q = tid; q < FX * FY; q += RCX * RCY) {
+      const int lx = q % FX, ly = q / FX;
+      const int fx = 2 * X0 - 1 + lx, fy = 2 * Y0 - 1 + ly;
+      T2 v;
+      v.x = 0;
+      v.y = 0;
+      if (fx >= 0 && fx < fg.nn[0] && fy >= 0 && fy < fg.nn[1]) v = rf[fx + fg.nn[0] * (long long)fy + fplane * z];
+      fs[ly][lx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const T wy = dy == 1 ? (T)1 : (T)0.5;
+      T ax = 0, ay = 0;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const T wx = dx == 1 ? (T)1 : (T)0.5;
+        const T2 v = fs[2 * cy + dy][2 * cx + dx];
+        ax += wx * v.x;
+        ay += wx * v.y;
+      }
+      p.x += wy * ax;
+      p.y += wy * ay;
+    }
+    return p;
+  };
+  T2 lo = plane(2 * Z0 - 1);
+  for (int Z = Z0; Z < zend; ++Z) {
+    const T2 mid = plane(2 * Z);
+    const T2 hi = plane(2 * Z + 1);
+    if (inside) {
+      T2 o;
+      o.x = (T)0.5 * lo.x + mid.x + (T)0.5 * hi.x;
+      o.y = (T)0.5 * lo.y + mid.y + (T)0.5 * hi.y;
+      bc[X + cg.nn[0] * (long long)Y + (long long)cg.nn[0] * cg.nn[1] * Z] = o;
+    }
+    lo = hi;
+  }
+}
+
 // x_f[i] += sum_I P[i, I] e_c[I], by coarse node: the thread of coarse node
 // (cx, cy, cz) updates the fine nodes 2c + o, o in {0, 1}^DIM, that exist.  A
 // fine node with odd coordinates along m axes takes the sum of its 2^m coarse
@@ -937,7 +1016,16 @@ __global__ void __launch_bounds__(1024)
   using T2 = typename V2<T>::type;
   __shared__ T2 xs[2][kCoarseLdsNodes];
   __shared__ T2 ds[kCoarseLdsNodes];
+  // the right-hand side and the cell coefficients are read from memory once:
+  // every step then touches LDS only (a grid of n nodes has fewer than n cells)
+  __shared__ T2 bs[kCoarseLdsNodes];
+  __shared__ T cs[kCoarseLdsNodes];
   const int n = (int)g.nnodes;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    bs[i] = b[i];
+    if (i < g.ncells) cs[i] = c[i];
+  }
+  __syncthreads();
   for (int k = 0; k < kCoarseDegree; ++k) {
     const int src = k & 1, dst = src ^ 1;
     const T al0 = (T)coef[4 * k + 0], al1 = (T)coef[4 * k + 1];
@@ -945,16 +1033,16 @@ __global__ void __launch_bounds__(1024)
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       int ix, iy, iz;
       node_ijk<DIM>(g, i, ix, iy, iz);
-      const T2 bb = b[i];
+      const T2 bb = bs[i];
       T dn0, dn1, x0 = 0, x1 = 0;
       if (k == 0) {
         T dg0, dg1;
-        diag_only<DIM, T>(g, c, ix, iy, iz, dg0, dg1);
+        diag_only<DIM, T>(g, cs, ix, iy, iz, dg0, dg1);
         dn0 = div_diag(be0 * bb.x, dg0);
         dn1 = div_diag(be1 * bb.y, dg1);
       } else {
         T w0[DIM == 3 ? 27 : 9], w1[DIM == 3 ? 27 : 9];
-        stencil<DIM, T>(g, c, ix, iy, iz, w0, w1);
+        stencil<DIM, T>(g, cs, ix, iy, iz, w0, w1);
         T y0 = 0, y1 = 0;
 #pragma unroll
         for (int tz = 0; tz < (DIM == 3 ? 3 : 1); ++tz) {
@@ -1378,8 +1466,21 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
   }
   PF_HIP_CHECK(hipGetLastError());
   Level<T>& C = H.lv[l + 1];
-  hipLaunchKernelGGL((k_restrict<DIM, T>), plane_grid(C.k), dim3(kT), 0, s, L.k, C.k,
-                     (const typename V2<T>::type*)L.r, C.b);
+  if (DIM == 3 && PF_RESTRICT_TILED) {
+    // coarse z-chunks: the longest power of two up to 16 planes that still
+    // gives half the stencils' workgroup target (PF_GMG_TILE_GROUPS overrides
+    // it as for the stencils)
+    const long long tiles = (long long)((C.k.nn[0] + RCX - 1) / RCX) * ((C.k.nn[1] + RCY - 1) / RCY);
+    const long long target = (tiled_min_groups() + 1) / 2;
+    int kz = 16;
+    while (kz > 1 && tiles * ((C.k.nn[2] + kz - 1) / kz) < target) kz /= 2;
+    const unsigned nb = (unsigned)(tiles * ((C.k.nn[2] + kz - 1) / kz));
+    hipLaunchKernelGGL((k_restrict3t<T>), dim3(nb), dim3(RCX * RCY), 0, s, L.k, C.k,
+                       (const typename V2<T>::type*)L.r, C.b, kz);
+  } else {
+    hipLaunchKernelGGL((k_restrict<DIM, T>), plane_grid(C.k), dim3(kT), 0, s, L.k, C.k,
+                       (const typename V2<T>::type*)L.r, C.b);
+  }
   PF_HIP_CHECK(hipGetLastError());
   PF_TRY((vcycle<DIM, T>(pb, H, l + 1, nullptr, nullptr, s)));
   hipLaunchKernelGGL((k_prolong_add<DIM, T>), plane_grid(C.k), dim3(kT), 0, s, L.k, C.k,
