@@ -112,16 +112,16 @@ def flops_per_element(dim):
 
 # FP64 flops per element counted for the roofline.  3-D: the counter value
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 of k_fused3<0, false>, x 64 lanes / 256^3
-# elements), 3072 -- 39 below the source-level count of flops_per_element(3)
-# because the compiler folds the constant point weights of the unrolled rows;
-# the executed count is the conservative one.  2-D: the source-level count.
-FLOPS_PER_ELEM = {3: 3072, 2: flops_per_element(2)}
+# elements), 3102 -- 9 below the source-level count of flops_per_element(3)
+# (the compiler folds some constant point weights of the unrolled rows); the
+# executed count is the one reported.  2-D: the source-level count.
+FLOPS_PER_ELEM = {3: 3102, 2: flops_per_element(2)}
 # The same counter for every 3-D element kernel of the residual family
 # (k_fused3<0..5>: residual, FD Jv, analytic Jv, VJP with all outputs, the
 # transposed-operator product alone, the previous-state and parameter product),
 # for the per-kernel FP64 rates reported beside the roofline.
-KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3072, "fd_jv": 3110, "analytic_jv": 5224, "vjp": 6993,
-                            "vjp_gU_only": 5571, "vjp_prev_and_params": 3634}
+KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3102, "fd_jv": 3142, "analytic_jv": 5200, "vjp": 7023,
+                            "vjp_gU_only": 5548, "vjp_prev_and_params": 3634}
 BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
 # HBM bytes moved by one pf_residual call (k_fused3<0, false> + k_fixup3<0>) on
@@ -133,8 +133,8 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1106307896,
-    "sources_sha256": "a1e7710951b783f3004b23519710bcacd101e39d564f231d374e32c238faedbb",
+    "bytes": 1106343880,
+    "sources_sha256": "c539f9d15ae3b3a2987390dad78ad40b1d33fe47fd27f54442e96b3e6fbf2700",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
                    "paper_2006_16764_amd/csrc/pf_internal.h")

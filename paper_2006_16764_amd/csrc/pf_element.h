@@ -128,15 +128,18 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // every Gauss plane gz: a loader that reads them from memory each time keeps
 // them out of registers between planes (quad3 passes register arrays).
 //
-// The element outputs are accumulated through acc: acc.s(o, a, v) adds v to
-// value-and-flux output o at corner a, acc.p(o, a, v) to value-only output o
-// (RegAcc: register arrays; StridedAcc: a lane's slots in memory).
+// The element outputs are accumulated through acc: acc.s(o, a, c1, v1, c2, v2)
+// adds c1 v1 + c2 v2 (two FMAs) to value-and-flux output o at corner a,
+// acc.p(o, a, c, v) adds c v to value-only output o (RegAcc: register arrays;
+// StridedAcc: a lane's slots in memory).
 template <int NS, int NP>
 struct RegAcc {
   double (&os)[NS > 0 ? NS : 1][8];
   double (&op)[NP > 0 ? NP : 1][8];
-  __device__ __forceinline__ void s(int o, int a, double v) { os[o][a] += v; }
-  __device__ __forceinline__ void p(int o, int a, double v) { op[o][a] += v; }
+  __device__ __forceinline__ void s(int o, int a, double c1, double v1, double c2, double v2) {
+    os[o][a] = fma(c2, v2, fma(c1, v1, os[o][a]));
+  }
+  __device__ __forceinline__ void p(int o, int a, double c, double v) { op[o][a] = fma(c, v, op[o][a]); }
 };
 // Output o, corner a at base_s[(o * 8 + a) * stride] (value-only outputs at
 // base_p likewise).
@@ -144,8 +147,14 @@ struct StridedAcc {
   double* base_s;
   double* base_p;
   int stride;
-  __device__ __forceinline__ void s(int o, int a, double v) { base_s[(o * 8 + a) * stride] += v; }
-  __device__ __forceinline__ void p(int o, int a, double v) { base_p[(o * 8 + a) * stride] += v; }
+  __device__ __forceinline__ void s(int o, int a, double c1, double v1, double c2, double v2) {
+    double& x = base_s[(o * 8 + a) * stride];
+    x = fma(c2, v2, fma(c1, v1, x));
+  }
+  __device__ __forceinline__ void p(int o, int a, double c, double v) {
+    double& x = base_p[(o * 8 + a) * stride];
+    x = fma(c, v, x);
+  }
 };
 
 template <int NG, int NV, int NS, int NP, class Phys, class Load, class Acc>
@@ -260,10 +269,10 @@ __device__ __forceinline__ void quad3g(const Geo& G, Load& load, Acc& acc, Phys&
       for (int o = 0; o < NS; ++o) {
         const double sx0 = rs[o][0] - rx[o] * ihx;
         const double sx1 = rs[o][1] + rx[o] * ihx;
-        S[o][0] += wb0 * sx0 - ry[o][0] * wih;
-        S[o][1] += wb0 * sx1 - ry[o][1] * wih;
-        S[o][2] += wb1 * sx0 + ry[o][0] * wih;
-        S[o][3] += wb1 * sx1 + ry[o][1] * wih;
+        S[o][0] = fma(-ry[o][0], wih, fma(wb0, sx0, S[o][0]));
+        S[o][1] = fma(-ry[o][1], wih, fma(wb0, sx1, S[o][1]));
+        S[o][2] = fma(ry[o][0], wih, fma(wb1, sx0, S[o][2]));
+        S[o][3] = fma(ry[o][1], wih, fma(wb1, sx1, S[o][3]));
         Zc[o][0] += wb0 * rz[o][0];
         Zc[o][1] += wb0 * rz[o][1];
         Zc[o][2] += wb1 * rz[o][0];
@@ -288,13 +297,13 @@ PF_UNROLL(PF_GY_UNROLL)
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
       for (int o = 0; o < NS; ++o) {
-        acc.s(o, a, bz0 * S[o][a] - Zc[o][a] * ihz);
-        acc.s(o, a + 4, bz1 * S[o][a] + Zc[o][a] * ihz);
+        acc.s(o, a, bz0, S[o][a], -ihz, Zc[o][a]);
+        acc.s(o, a + 4, bz1, S[o][a], ihz, Zc[o][a]);
       }
 #pragma unroll
       for (int o = 0; o < NP; ++o) {
-        acc.p(o, a, bz0 * P[o][a]);
-        acc.p(o, a + 4, bz1 * P[o][a]);
+        acc.p(o, a, bz0, P[o][a]);
+        acc.p(o, a + 4, bz1, P[o][a]);
       }
     }
   }
@@ -393,10 +402,10 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
     for (int o = 0; o < NS; ++o) {
       const double sx0 = rs[o][0] - rx[o] * ihx;
       const double sx1 = rs[o][1] + rx[o] * ihx;
-      os[o][0] += wb0 * sx0 - ry[o][0] * wih;
-      os[o][1] += wb0 * sx1 - ry[o][1] * wih;
-      os[o][2] += wb1 * sx0 + ry[o][0] * wih;
-      os[o][3] += wb1 * sx1 + ry[o][1] * wih;
+      os[o][0] = fma(-ry[o][0], wih, fma(wb0, sx0, os[o][0]));
+      os[o][1] = fma(-ry[o][1], wih, fma(wb0, sx1, os[o][1]));
+      os[o][2] = fma(ry[o][0], wih, fma(wb1, sx0, os[o][2]));
+      os[o][3] = fma(ry[o][1], wih, fma(wb1, sx1, os[o][3]));
     }
 #pragma unroll
     for (int o = 0; o < NP; ++o) {
@@ -531,11 +540,12 @@ struct PhysJvp {
     double Hv[3] = {0.0, 0.0, 0.0};
     double dav;
     A.hvp(gg[0], gg[1], G, Hv, dav);
-    const double p2 = phi * phi;
-    const double om = 1.0 - p2;
-    const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;  // dR/dphi
-    const double Ru = -G.lam * om * om;                              // dR/du
-    s[0] = (2.0 * A.a * dav * dphi + A.a2 * tp) * G.idtm - (Rp * tp + Ru * tu);
+    // dR/dphi = 1 - 3 phi^2 + 4 lambda phi (1 - phi^2) u = (1 - phi^2)(3 + 4 lambda phi u) - 2,
+    // dR/du = -lambda (1 - phi^2)^2
+    const double om = fma(-phi, phi, 1.0);
+    const double Rp = fma(om, fma(4.0 * G.lam * phi, u, 3.0), -2.0);
+    const double Rv = fma(Rp, tp, (-G.lam * om) * (om * tu));  // dR/dphi tp + dR/du tu
+    s[0] = fma(fma((A.a + A.a) * dav, dphi, A.a2 * tp), G.idtm, -Rv);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? Hv[k] : 0.0;
   }
@@ -622,12 +632,11 @@ struct PhysVjpU {
     double Hw[3] = {0.0, 0.0, 0.0};
     double daw;
     A.hvp(gg[0], gg[1], G, Hw, daw);
-    const double p2 = phi * phi;
-    const double om = 1.0 - p2;
-    const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
-    const double m = 2.0 * A.a * dphi * G.idtm * w1;
-    s[0] = w1 * (A.a2 * G.idtm - Rp);
-    p[0] = w1 * G.lam * om * om;
+    const double om = fma(-phi, phi, 1.0);
+    const double Rp = fma(om, fma(4.0 * G.lam * phi, u, 3.0), -2.0);  // as in PhysJvp
+    const double m = (A.a * dphi) * ((G.idtm + G.idtm) * w1);
+    s[0] = w1 * fma(A.a2, G.idtm, -Rp);
+    p[0] = (w1 * G.lam) * (om * om);
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m * A.b, gg[0][k] * A.gm[k], Hw[k]) : 0.0;
   }
