@@ -508,7 +508,8 @@ __global__ void __launch_bounds__(kT)
 // mesh) is staged in LDS once and restricted along x and y there (weights 1/2,
 // 1, 1/2); coarse plane Z then combines the fine planes 2Z - 1, 2Z, 2Z + 1
 // with the z weights, the plane 2Z + 1 being carried to Z + 1.  Fine rows are
-// read once, coalesced, instead of by up to 8 coarse threads each.
+// read once, coalesced, instead of by up to 8 coarse threads each, and the
+// next fine plane's loads are in flight while the current one is summed.
 constexpr int RCX = 32, RCY = 8;
 
 template <class T>
@@ -517,7 +518,6 @@ __global__ void __launch_bounds__(RCX * RCY)
                  typename V2<T>::type* __restrict__ bc, int kz) {
   using T2 = typename V2<T>::type;
   constexpr int FX = 2 * RCX + 1, FY = 2 * RCY + 1;
-  __shared__ T2 fs[FY][FX];
   const int tid = threadIdx.x;
   const int cx = tid % RCX, cy = tid / RCX;
   const int ntx = (cg.nn[0] + RCX - 1) / RCX, nty = (cg.nn[1] + RCY - 1) / RCY;
@@ -528,24 +528,45 @@ __global__ void __launch_bounds__(RCX * RCY)
   const bool inside = X < cg.nn[0] && Y < cg.nn[1];
   const int zend = min(Z0 + kz, cg.nn[2]);
   const long long fplane = (long long)fg.nn[0] * fg.nn[1];
-  // x-y restriction of fine plane z at this thread's coarse column (0 for a
-  // plane outside the mesh)
+  // The fine planes 2 Z0 - 1 .. 2 zend - 1 are streamed in order, each staged
+  // in one of two LDS buffers from registers loaded while the previous plane
+  // was restricted (the node offsets of a thread's slots do not change with z).
+  constexpr int NQ = FX * FY, NR = (NQ + RCX * RCY - 1) / (RCX * RCY);
+  __shared__ T2 fsd[2][FY][FX];
+  int off[NR];
+  bool okq[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int q = tid + j * RCX * RCY;
+    const int fx = 2 * X0 - 1 + q % FX, fy = 2 * Y0 - 1 + q / FX;
+    okq[j] = q < NQ && fx >= 0 && fx < fg.nn[0] && fy >= 0 && fy < fg.nn[1];
+    off[j] = okq[j] ? fx + fg.nn[0] * fy : 0;
+  }
+  T2 pf[NR];
+  auto fetch = [&](int z) {
+    const bool zin = z >= 0 && z < fg.nn[2];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      pf[j].x = 0;
+      pf[j].y = 0;
+      if (zin && okq[j]) pf[j] = rf[off[j] + fplane * z];
+    }
+  };
+  const int zlast = 2 * (zend - 1) + 1;  // last fine plane this chunk reads
+  int buf = 0;
+  // x-y restriction of fine plane z (0 for a plane outside the mesh), whose
+  // values are in pf; the next plane's loads are issued before the sums
   auto plane = [&](int z) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      const int q = tid + j * RCX * RCY;
+      if (q < NQ) fsd[buf][q / FX][q % FX] = pf[j];
+    }
+    __syncthreads();
+    if (z + 1 <= zlast) fetch(z + 1);
     T2 p;
     p.x = 0;
     p.y = 0;
-    if (z < 0 || z >= fg.nn[2]) return p;
-    __syncthreads();  // the previous plane's reads are done
-    for (int q = tid; q < FX * FY; q += RCX * RCY) {
-      const int lx = q % FX, ly = q / FX;
-      const int fx = 2 * X0 - 1 + lx, fy = 2 * Y0 - 1 + ly;
-      T2 v;
-      v.x = 0;
-      v.y = 0;
-      if (fx >= 0 && fx < fg.nn[0] && fy >= 0 && fy < fg.nn[1]) v = rf[fx + fg.nn[0] * (long long)fy + fplane * z];
-      fs[ly][lx] = v;
-    }
-    __syncthreads();
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
       const T wy = dy == 1 ? (T)1 : (T)0.5;
@@ -553,15 +574,17 @@ __global__ void __launch_bounds__(RCX * RCY)
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
         const T wx = dx == 1 ? (T)1 : (T)0.5;
-        const T2 v = fs[2 * cy + dy][2 * cx + dx];
+        const T2 v = fsd[buf][2 * cy + dy][2 * cx + dx];
         ax += wx * v.x;
         ay += wx * v.y;
       }
       p.x += wy * ax;
       p.y += wy * ay;
     }
+    buf ^= 1;
     return p;
   };
+  fetch(2 * Z0 - 1);
   T2 lo = plane(2 * Z0 - 1);
   for (int Z = Z0; Z < zend; ++Z) {
     const T2 mid = plane(2 * Z);
@@ -848,6 +871,18 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
   fetch_x(z0 + 1);
   fetch_c(z0);
   const long long ibase = ix + (long long)g.nn[0] * iy;
+  // FP32 residual and Chebyshev steps: the node's own right-hand side one
+  // plane ahead in registers, so that the compute phase waits on one global
+  // read fewer (measured: the last step, which also reads d and writes FP64,
+  // and the FP64 sweeps are slower with it)
+  constexpr bool kPreB = sizeof(T) == 4 && OP <= 1 && FL != (kReadD | kWriteD);
+  T2 nb{};
+  auto fetch_bd = [&](int z) {
+    if constexpr (kPreB) {
+      if (inside) nb = b[ibase + plane_n * z];
+    }
+  };
+  fetch_bd(z0);
   for (int z = z0; z < zend; ++z) {
     const int k = z - z0;
     const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
@@ -855,10 +890,13 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
     store_x(sp);  // plane z + 1
     store_c(cp);  // cell plane z
     __syncthreads();
+    const T2 cur_b = nb;
     if (z + 1 < zend) {
       fetch_x(z + 2);
       fetch_c(z + 1);
+      fetch_bd(z + 1);
     }
+    (void)cur_b;
     if (inside) {
       // y = A x for both blocks, grouped by the corner-difference pattern p
       // of the stencil offset (bit 0: x offset, 1: y, 2: z):
@@ -975,7 +1013,7 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
         bb.y = (T)rv.y;
         A.bout[i] = bb;
       } else {
-        bb = b[i];
+        bb = kPreB ? cur_b : b[i];
       }
       const T r0 = bb.x - y0, r1 = bb.y - y1;
       if (OP == 0) {
