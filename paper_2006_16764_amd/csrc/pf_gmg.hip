@@ -784,14 +784,20 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
     okc[j] = q < NQC && cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1];
     offc[j] = okc[j] ? cx + g.n[0] * cy : 0;
   }
-  T2 rx[NX];
+  // a fetched halo node plane, held in registers until stored to the ring;
+  // zero start: also the raw right-hand side and diagonal of its nodes and
+  // whether they are in the mesh
+  struct XPlane {
+    T2 rx[NX];
+    double2 rr[OP == 3 ? NX : 1];
+    T rdg[ZS ? NX : 1];
+    bool rin[ZS ? NX : 1];
+    int fz;
+  };
+  XPlane xa, xb;  // xb: the prologue's second plane only
   T rc[NC];
-  // zero start: raw right-hand side and diagonal of the fetched halo plane, the
-  // in-plane cell counts of the halo nodes (u-block diagonal) and the plane
-  double2 rr[OP == 3 ? NX : 1];
-  T rdg[ZS ? NX : 1], cxy[ZS ? NX : 1];
-  bool rin[ZS ? NX : 1];
-  int fz = 0;
+  // zero start: the in-plane cell counts of the halo nodes (u-block diagonal)
+  T cxy[ZS ? NX : 1];
   if constexpr (ZS) {
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
@@ -801,45 +807,45 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
                (T)((gy - 1 >= 0 ? 1 : 0) + (gy < g.n[1] ? 1 : 0));
     }
   }
-  auto fetch_x = [&](int z) {
+  auto fetch_x = [&](XPlane& f, int z) {
     const bool zin = z >= 0 && z < g.nn[2];
     const long long po = plane_n * (zin ? z : 0);
-    fz = z;
+    f.fz = z;
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
-      rx[j].x = 0;
-      rx[j].y = 0;
+      f.rx[j].x = 0;
+      f.rx[j].y = 0;
       if constexpr (ZS) {
-        rin[j] = zin && okx[j];
-        rdg[j] = 1;
-        if constexpr (OP == 3) rr[j] = make_double2(0.0, 0.0);
-        if (rin[j]) {
-          rdg[j] = A.dg[po + offx[j]];
-          if constexpr (OP == 3) rr[j] = A.r64[po + offx[j]];
-          else rx[j] = b[po + offx[j]];
+        f.rin[j] = zin && okx[j];
+        f.rdg[j] = 1;
+        if constexpr (OP == 3) f.rr[j] = make_double2(0.0, 0.0);
+        if (f.rin[j]) {
+          f.rdg[j] = A.dg[po + offx[j]];
+          if constexpr (OP == 3) f.rr[j] = A.r64[po + offx[j]];
+          else f.rx[j] = b[po + offx[j]];
         }
       } else {
-        if (zin && okx[j]) rx[j] = x[po + offx[j]];
+        if (zin && okx[j]) f.rx[j] = x[po + offx[j]];
       }
     }
   };
-  auto store_x = [&](int slot) {
+  auto store_x = [&](const XPlane& f, int slot) {
     T czf = 1;
-    if constexpr (ZS) czf = (T)((fz - 1 >= 0 ? 1 : 0) + (fz < g.n[2] ? 1 : 0));
+    if constexpr (ZS) czf = (T)((f.fz - 1 >= 0 ? 1 : 0) + (f.fz < g.n[2] ? 1 : 0));
 #pragma unroll
     for (int j = 0; j < NX; ++j) {
       const int q = tid + j * SBX * SBY;
-      T2 v = rx[j];
+      T2 v = f.rx[j];
       if constexpr (ZS) {
         // x1 = zb D^-1 b at the halo node (0 outside the mesh)
-        T2 bv = rx[j];
+        T2 bv = f.rx[j];
         if constexpr (OP == 3) {
-          bv.x = (T)rr[j].x;
-          bv.y = (T)rr[j].y;
+          bv.x = (T)f.rr[j].x;
+          bv.y = (T)f.rr[j].y;
         }
         const T dg1 = (T)g.Ae[1][0] * (cxy[j] * czf);
-        v.x = rin[j] ? div_diag(A.zb0 * bv.x, rdg[j]) : (T)0;
-        v.y = rin[j] ? div_diag(A.zb1 * bv.y, dg1) : (T)0;
+        v.x = f.rin[j] ? div_diag(A.zb0 * bv.x, f.rdg[j]) : (T)0;
+        v.y = f.rin[j] ? div_diag(A.zb1 * bv.y, dg1) : (T)0;
         if (ZSB && q < NQX) (&bs[slot][0][0])[q] = bv;
       }
       if (q < NQX) (&xs[slot][0][0])[q] = v;
@@ -861,14 +867,15 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
       if (q < NQC) (&cs[slot][0][0])[q] = rc[j];
     }
   };
-  // ring slots: node plane z lives in slot (z - z0 + 1) % 3, cell plane zc in (zc - z0 + 1) & 1
-  fetch_x(z0 - 1);
-  store_x(0);
-  fetch_x(z0);
-  store_x(1);
+  // ring slots: node plane z lives in slot (z - z0 + 1) % 3, cell plane zc in
+  // (zc - z0 + 1) & 1.  The prologue's three planes are loaded together.
+  fetch_x(xa, z0 - 1);
+  fetch_x(xb, z0);
   fetch_c(z0 - 1);
+  store_x(xa, 0);
+  store_x(xb, 1);
   store_c(0);
-  fetch_x(z0 + 1);
+  fetch_x(xa, z0 + 1);
   fetch_c(z0);
   const long long ibase = ix + (long long)g.nn[0] * iy;
   // FP32 residual and Chebyshev steps: the node's own right-hand side one
@@ -887,12 +894,12 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
     const int k = z - z0;
     const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
     const int cm = k & 1, cp = cm ^ 1;
-    store_x(sp);  // plane z + 1
-    store_c(cp);  // cell plane z
+    store_x(xa, sp);  // plane z + 1
+    store_c(cp);      // cell plane z
     __syncthreads();
     const T2 cur_b = nb;
     if (z + 1 < zend) {
-      fetch_x(z + 2);
+      fetch_x(xa, z + 2);
       fetch_c(z + 1);
       fetch_bd(z + 1);
     }
