@@ -90,38 +90,39 @@ def flops_per_element(dim):
     matrices; Gauss part for the phi equation with phi interpolated with its
     gradient, u and (phi - phi^n)/(theta dt) as values, one output with value
     and flux parts, point sums taken with the x weights only and scaled per
-    row.  Pointwise physics 50 flops in 3-D including a reciprocal with two
-    Newton steps; the 3-D residual that also forms the cell mean of a^2 for the
-    preconditioner is a separate kernel with one more FMA per point and per
-    row.  The 2-D kernel always forms that mean: physics 40 flops, row weights
-    4.  Interpolation uses q0 + b1 (q1 - q0), so each point costs one FMA per
-    interpolated value.
+    row.  Pointwise physics 45 flops in 3-D including a reciprocal with one
+    Newton step and the flux factors t_k = (a^2 - aqc S/Q) + aqc g_k^2; the 3-D
+    residual that also forms the cell mean of a^2 for the preconditioner is a
+    separate kernel with one more FMA per point and per row.  The 2-D kernel
+    always forms that mean: physics 36 flops, row weights 4.  Interpolation
+    uses q0 + b1 (q1 - q0), so each point costs one FMA per interpolated value.
     3-D: corner differences and scalings 48 + linear part 264 + 3 planes x
     (interpolation 40 + contraction 32) + 9 rows x (interpolation 26 + x
     differences 6 + weights 3 + contraction 30) + 27 points x (interpolation 10
-    + physics 50 + contraction 14) = 3111.
+    + physics 45 + contraction 14) = 2976.
     2-D: corner differences and scalings 24 + linear part 88 + 3 rows x
     (interpolation 20 + x differences 5 + weights 4 + contraction 22) + 9 points
-    x (interpolation 8 + physics 40 + contraction 10) = 787.
+    x (interpolation 8 + physics 36 + contraction 10) = 751.
     The scalings include the time weight theta applied to the element vector.
     """
     if dim == 3:
-        return 48 + 264 + 3 * (40 + 32) + 9 * (26 + 6 + 3 + 30) + 27 * (10 + 50 + 14)
-    return 24 + 88 + 3 * (20 + 5 + 4 + 22) + 9 * (8 + 40 + 10)
+        return 48 + 264 + 3 * (40 + 32) + 9 * (26 + 6 + 3 + 30) + 27 * (10 + 45 + 14)
+    return 24 + 88 + 3 * (20 + 5 + 4 + 22) + 9 * (8 + 36 + 10)
 
 
 # FP64 flops per element counted for the roofline.  3-D: the counter value
 # (rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 of k_fused3<0, false>, x 64 lanes / 256^3
-# elements), 3102 -- 9 below the source-level count of flops_per_element(3)
-# (the compiler folds some constant point weights of the unrolled rows); the
-# executed count is the one reported.  2-D: the source-level count.
-FLOPS_PER_ELEM = {3: 3102, 2: flops_per_element(2)}
+# elements), 2913 -- 63 below the source-level count of flops_per_element(3)
+# (the compiler folds constant point weights of the unrolled rows and shares
+# some products between the three points of a row); the executed count is the
+# one reported.  2-D: the source-level count.
+FLOPS_PER_ELEM = {3: 2913, 2: flops_per_element(2)}
 # The same counter for every 3-D element kernel of the residual family
 # (k_fused3<0..5>: residual, FD Jv, analytic Jv, VJP with all outputs, the
 # transposed-operator product alone, the previous-state and parameter product),
 # for the per-kernel FP64 rates reported beside the roofline.
-KERNEL_FLOPS_PER_ELEM_3D = {"residual": 3102, "fd_jv": 3142, "analytic_jv": 5200, "vjp": 7023,
-                            "vjp_gU_only": 5548, "vjp_prev_and_params": 3634}
+KERNEL_FLOPS_PER_ELEM_3D = {"residual": 2913, "fd_jv": 2953, "analytic_jv": 5092, "vjp": 6915,
+                            "vjp_gU_only": 5440, "vjp_prev_and_params": 3526}
 BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
 # HBM bytes moved by one pf_residual call (k_fused3<0, false> + k_fixup3<0>) on
@@ -133,8 +134,8 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1106343880,
-    "sources_sha256": "c539f9d15ae3b3a2987390dad78ad40b1d33fe47fd27f54442e96b3e6fbf2700",
+    "bytes": 1097823656,
+    "sources_sha256": "57ad2e52fcd416364a5c42d2b354b0dd959bdcafe9ea819949b5272f5281a854",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
                    "paper_2006_16764_amd/csrc/pf_internal.h")

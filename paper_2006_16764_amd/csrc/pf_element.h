@@ -115,6 +115,16 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
+// The same with one Newton step.  Measured on gfx950 over 4M positive values
+// spanning 60 binades: the estimate is within 4.6e-8 relative, one step within
+// 2.2e-15 (about 10 ulp), two steps correctly rounded in every case.  Used for
+// the anisotropy's 1/Q, where 2.2e-15 is far below every tolerance the
+// results are held to.
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // ----------------------------------------------------------------- Gauss-rule part, 3-D
 // NG fields interpolated with value and gradient (ng), NV fields with value
 // only (nv); NS outputs with value and flux parts (os), NP value-only outputs
@@ -428,6 +438,9 @@ struct Aniso {
   // gm_k = g_k^2 - S/Q and t_k with J_k = g_k t_k, t_k = a^2 + aqc gm_k
   // (da/dg_k = b g_k gm_k).
   double q, S, iQ, iQ2, a, a2, b, aqc, SQ, g2[3], gm[3], t[3], J[3];
+  // kFluxOnly: only J is used afterwards (the residual): t_k is formed as
+  // (a^2 - aqc S/Q) + aqc g_k^2, one FMA per component, and gm is not formed
+  template <bool kFluxOnly = false>
   __device__ __forceinline__ void flux(const double* g, const Geo& G) {
     q = 0.0;
     S = 0.0;
@@ -437,18 +450,27 @@ struct Aniso {
       q += g2[k];
       S = fma(g2[k], g2[k], S);
     }
-    iQ = rcp_nr(q + G.delta2);
+    iQ = rcp_nr1(q + G.delta2);
     iQ2 = iQ * iQ;
     a = fma(G.e4x4 * S, iQ2, G.a0);
     SQ = S * iQ;
     a2 = a * a;
     b = G.e16 * iQ2;
     aqc = (a * q) * b;
+    if constexpr (kFluxOnly) {
+      const double K0 = fma(-aqc, SQ, a2);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      gm[k] = g2[k] - SQ;
-      t[k] = fma(aqc, gm[k], a2);
-      J[k] = g[k] * t[k];
+      for (int k = 0; k < DIM; ++k) {
+        t[k] = fma(aqc, g2[k], K0);
+        J[k] = g[k] * t[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        gm[k] = g2[k] - SQ;
+        t[k] = fma(aqc, gm[k], a2);
+        J[k] = g[k] * t[k];
+      }
     }
   }
   // da/dg_k = 16 eps4 g_k (g_k^2 - S/Q)/Q^2 (after flux())
@@ -511,7 +533,7 @@ struct PhysResidual {
                                              double*) {
     const double phi = gv[0], u = vv[0], dphi_dt = vv[1];
     Aniso<DIM> A;
-    A.flux(gg[0], G);
+    A.template flux<true>(gg[0], G);
     a2 = A.a * A.a;
     const double om = fma(-phi, phi, 1.0);
     const double R = om * fma(-G.lam * om, u, phi);  // phi - phi^3 - lambda (1-phi^2)^2 u

@@ -23,11 +23,11 @@ def test_vcycle_bytes_by_hand():
 
 def test_flop_counts():
     # source-level count of the plain 3-D residual (no preconditioner
-    # coefficient); the counter value of the compiled kernel is 9 below it
-    assert bench.flops_per_element(3) == 3111
-    assert bench.FLOPS_PER_ELEM[3] == bench.KERNEL_FLOPS_PER_ELEM_3D["residual"] == 3102
-    assert bench.flops_per_element(3) - bench.FLOPS_PER_ELEM[3] == 9
-    assert bench.FLOPS_PER_ELEM[2] == bench.flops_per_element(2) == 787
+    # coefficient); the counter value of the compiled kernel is 63 below it
+    assert bench.flops_per_element(3) == 2976
+    assert bench.FLOPS_PER_ELEM[3] == bench.KERNEL_FLOPS_PER_ELEM_3D["residual"] == 2913
+    assert bench.flops_per_element(3) - bench.FLOPS_PER_ELEM[3] == 63
+    assert bench.FLOPS_PER_ELEM[2] == bench.flops_per_element(2) == 751
 
 
 def test_traffic_figure_is_tied_to_the_sources():
