@@ -121,8 +121,8 @@ FLOPS_PER_ELEM = {3: 2913, 2: flops_per_element(2)}
 # (k_fused3<0..5>: residual, FD Jv, analytic Jv, VJP with all outputs, the
 # transposed-operator product alone, the previous-state and parameter product),
 # for the per-kernel FP64 rates reported beside the roofline.
-KERNEL_FLOPS_PER_ELEM_3D = {"residual": 2913, "fd_jv": 2953, "analytic_jv": 5092, "vjp": 6915,
-                            "vjp_gU_only": 5440, "vjp_prev_and_params": 3526}
+KERNEL_FLOPS_PER_ELEM_3D = {"residual": 2913, "fd_jv": 2953, "analytic_jv": 4795, "vjp": 5862,
+                            "vjp_gU_only": 4927, "vjp_prev_and_params": 3067}
 BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 
 # HBM bytes moved by one pf_residual call (k_fused3<0, false> + k_fixup3<0>) on
@@ -134,8 +134,8 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1097865432,
-    "sources_sha256": "57ad2e52fcd416364a5c42d2b354b0dd959bdcafe9ea819949b5272f5281a854",
+    "bytes": 1097772344,
+    "sources_sha256": "840fedd427caebe7baa05c09ad13d3607b8f52d73c235d5f46164ee98717ae32",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
                    "paper_2006_16764_amd/csrc/pf_internal.h")

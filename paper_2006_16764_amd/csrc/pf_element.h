@@ -477,16 +477,25 @@ struct Aniso {
   __device__ __forceinline__ double dadg(const double* g, int k, const Geo&) const {
     return b * (g[k] * gm[k]);
   }
-  // Directional derivative along v (after flux()): Hv = (dJ/dg) v, the Hessian
-  // of a^2 |g|^2 / 2 times v (symmetric), and da = (da/dg) . v.  Forward-mode
-  // differentiation of flux(), with gv = g.v and g3v = sum g_k^3 v_k:
+  // Directional derivative along v (after flux()): out = (dJ/dg) v, the
+  // Hessian of a^2 |g|^2 / 2 times v (symmetric), plus extra g_k (g_k^2 - S/Q)
+  // when kExtra (the transposed product adds that multiple of da/dg), and
+  // da = (da/dg) . v.  Forward-mode differentiation of flux(), with gv = g.v
+  // and g3v = sum g_k^3 v_k:
   //   da = b (g3v - (S/Q) gv),  d(a^2) = 2 a da,  dq = 2 gv,
   //   d(S/Q) = (4 g3v - (S/Q) dq)/Q,
   //   d(aqc) = b (da q + a dq (1 - 2 q/Q))   (db = -2 b dq/Q),
-  //   dt_k = d(a^2) + d(aqc) gm_k + aqc (2 g_k v_k - d(S/Q)),
-  //   (Hv)_k = v_k t_k + g_k dt_k.
-  __device__ __forceinline__ void hvp(const double* g, const double* v, const Geo&, double* Hv,
-                                      double& da) const {
+  //   dt_k = d(a^2) + d(aqc) gm_k + 2 aqc g_k v_k - aqc d(S/Q),
+  //   (Hv)_k = v_k t_k + g_k dt_k,
+  // regrouped by component as
+  //   out_k = v_k c_k + g_k (D g_k^2 + K1),  c_k = (a^2 - aqc S/Q) + 3 aqc g_k^2,
+  //   D = d(aqc) + extra,  K1 = d(a^2) - aqc d(S/Q) - D S/Q:
+  // c_k depends on the primal only, three operations per component, and gm,
+  // t are not needed.
+  // gvo = g.v and gmv = sum g_k gm_k v_k = g3v - (S/Q) gv are returned too.
+  template <bool kExtra>
+  __device__ __forceinline__ void hvp_c(const double* g, const double* v, double extra,
+                                        double* out, double& da, double& gvo, double& gmv) const {
     double gv = 0.0, g3v = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -494,18 +503,19 @@ struct Aniso {
       gv += gvk;
       g3v = fma(g2[k], gvk, g3v);
     }
-    da = b * fma(-SQ, gv, g3v);
+    gvo = gv;
+    gmv = fma(-SQ, gv, g3v);
+    da = b * gmv;
     const double dq = gv + gv;
     const double da2 = (a + a) * da;
     const double dSQ = iQ * fma(4.0, g3v, -SQ * dq);
     const double daqc = b * fma(da, q, (a * dq) * fma(-2.0 * q, iQ, 1.0));
-    const double K = fma(-aqc, dSQ, da2);
-    const double aqc2 = aqc + aqc;
+    const double D = kExtra ? daqc + extra : daqc;
+    const double K1 = fma(-D, SQ, fma(-aqc, dSQ, da2));
+    const double K0 = fma(-aqc, SQ, a2);
+    const double aqc3 = 3.0 * aqc;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double dt = fma(daqc, gm[k], fma(aqc2 * g[k], v[k], K));
-      Hv[k] = fma(v[k], t[k], g[k] * dt);
-    }
+    for (int k = 0; k < DIM; ++k) out[k] = fma(v[k], fma(aqc3, g2[k], K0), g[k] * fma(D, g2[k], K1));
   }
 };
 
@@ -560,8 +570,8 @@ struct PhysJvp {
     Aniso<DIM> A;
     A.flux(gg[0], G);
     double Hv[3] = {0.0, 0.0, 0.0};
-    double dav;
-    A.hvp(gg[0], gg[1], G, Hv, dav);
+    double dav, gtv, gmv;
+    A.template hvp_c<false>(gg[0], gg[1], 0.0, Hv, dav, gtv, gmv);
     // dR/dphi = 1 - 3 phi^2 + 4 lambda phi (1 - phi^2) u = (1 - phi^2)(3 + 4 lambda phi u) - 2,
     // dR/du = -lambda (1 - phi^2)^2
     const double om = fma(-phi, phi, 1.0);
@@ -602,9 +612,6 @@ struct PhysVjp {
     const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
     Aniso<DIM> A;
     A.flux(gg[0], G);
-    double Hw[3] = {0.0, 0.0, 0.0};
-    double daw;
-    A.hvp(gg[0], gg[1], G, Hw, daw);
     const double p2 = phi * phi;
     const double om = 1.0 - p2;
     const double Rp = 1.0 - 3.0 * p2 + 4.0 * G.lam * phi * om * u;
@@ -612,24 +619,19 @@ struct PhysVjp {
     s[0] = w1 * (A.a2 * G.idtm - Rp);
     p[0] = w1 * G.lam * om * om;
     p[1] = -w1 * A.a2 * G.idtm;
-    // parameter derivatives: da/deps4 = -3 + 4 S/Q^2; d(da/dg_k)/deps4 = dae_k = 16 g_k gm_k/Q^2, and
-    // da/dg_k = eps4 dae_k; J_k = a^2 g_k + a q da/dg_k, so
-    // dJ_k/deps4 = 2 a ae g_k + ae q da/dg_k + a q dae_k
+    // flux part: H w + m da/dg, da/dg_k = b g_k gm_k
+    double fw[3] = {0.0, 0.0, 0.0};
+    double daw, gw, gmw;
+    A.template hvp_c<true>(gg[0], gg[1], m * A.b, fw, daw, gw, gmw);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fw[k] : 0.0;
+    // parameter derivatives: da/deps4 = ae = -3 + 4 S/Q^2; d(da/dg_k)/deps4 = dae_k =
+    // 16 g_k gm_k/Q^2, and da/dg_k = eps4 dae_k; J_k = a^2 g_k + a q da/dg_k, so
+    // dJ_k/deps4 = 2 a ae g_k + (ae q eps4 + a q) dae_k and, summed against w,
+    // w . dJ/deps4 = 2 a ae (g.w) + (ae q eps4 + a q) 16/Q^2 sum_k g_k gm_k w_k
     const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
-    const double c16 = 16.0 * A.iQ2, tae = 2.0 * A.a * ae, aeq = ae * A.q, aq = A.a * A.q;
-    double Je_w = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const double gk = gg[0][k];
-      const double ggm = gk * A.gm[k];
-      const double dae = c16 * ggm;
-      const double dak = A.b * ggm;
-      const double Je = fma(tae, gk, fma(aeq, dak, aq * dae));
-      Je_w = fma(Je, gg[1][k], Je_w);
-      f[0][k] = Hw[k] + m * dak;
-    }
-#pragma unroll
-    for (int k = DIM; k < 3; ++k) f[0][k] = 0.0;
+    const double C16 = fma(ae * A.q, G.eps4, A.a * A.q) * (16.0 * A.iQ2);
+    const double Je_w = fma((A.a + A.a) * ae, gw, C16 * gmw);
     pe = m * ae + Je_w;
     pl = w1 * om * om * u;
   }
@@ -651,16 +653,17 @@ struct PhysVjpU {
     const double phi = gv[0], w1 = gv[1], u = vv[0], dphi = vv[1];
     Aniso<DIM> A;
     A.flux(gg[0], G);
-    double Hw[3] = {0.0, 0.0, 0.0};
-    double daw;
-    A.hvp(gg[0], gg[1], G, Hw, daw);
     const double om = fma(-phi, phi, 1.0);
     const double Rp = fma(om, fma(4.0 * G.lam * phi, u, 3.0), -2.0);  // as in PhysJvp
     const double m = (A.a * dphi) * ((G.idtm + G.idtm) * w1);
     s[0] = w1 * fma(A.a2, G.idtm, -Rp);
     p[0] = (w1 * G.lam) * (om * om);
+    // H w + m da/dg = H w + m b g_k gm_k
+    double fw[3] = {0.0, 0.0, 0.0};
+    double daw, gw, gmw;
+    A.template hvp_c<true>(gg[0], gg[1], m * A.b, fw, daw, gw, gmw);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fma(m * A.b, gg[0][k] * A.gm[k], Hw[k]) : 0.0;
+    for (int k = 0; k < 3; ++k) f[0][k] = (k < DIM) ? fw[k] : 0.0;
   }
 };
 
@@ -696,21 +699,17 @@ struct PhysVjpPrev {
     const double om = 1.0 - phi * phi;
     const double m = 2.0 * A.a * dphi * G.idtm * w1;
     p[0] = -w1 * A.a2 * G.idtm;
-    // da/deps4 = -3 + 4 S/Q^2; d(da/dg_k)/deps4 = dae_k = 16 g_k gm_k/Q^2, and
-    // da/dg_k = eps4 dae_k; J_k = a^2 g_k + a q da/dg_k, so
-    // dJ_k/deps4 = 2 a ae g_k + ae q da/dg_k + a q dae_k
-    const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
-    const double c16 = 16.0 * A.iQ2, tae = 2.0 * A.a * ae, aeq = ae * A.q, aq = A.a * A.q;
-    double Je_w = 0.0;
+    // w . dJ/deps4 as in PhysVjp: 2 a ae (g.w) + (ae q eps4 + a q) 16/Q^2 sum_k g_k gm_k w_k
+    double gw = 0.0, g3w = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double gk = gg[0][k];
-      const double ggm = gk * A.gm[k];
-      const double dae = c16 * ggm;
-      const double dak = A.b * ggm;
-      const double Je = fma(tae, gk, fma(aeq, dak, aq * dae));
-      Je_w = fma(Je, gg[1][k], Je_w);
+      const double gwk = gg[0][k] * gg[1][k];
+      gw += gwk;
+      g3w = fma(A.g2[k], gwk, g3w);
     }
+    const double ae = fma(4.0 * A.S, A.iQ2, -3.0);
+    const double C16 = fma(ae * A.q, G.eps4, A.a * A.q) * (16.0 * A.iQ2);
+    const double Je_w = fma((A.a + A.a) * ae, gw, C16 * fma(-A.SQ, gw, g3w));
     pe = m * ae + Je_w;
     pl = w1 * om * om * u;
   }
