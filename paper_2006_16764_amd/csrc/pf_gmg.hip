@@ -35,6 +35,21 @@ namespace pf {
 namespace {
 
 constexpr int kT = 256;
+
+// Workgroup barrier for LDS only: this wave's LDS operations have completed
+// and no memory access is moved across it by the compiler, but global loads
+// and stores issued before it may still be in flight.  __syncthreads() also
+// waits for those (a workgroup release fence), which exposes the latency of
+// every store a wave issued just before it.  Used where the threads of a
+// workgroup exchange data through LDS only (the tiled sweeps and the tiled
+// restriction: no thread reads another's global writes within a launch).
+#ifndef PF_LDS_BARRIER
+#define PF_LDS_BARRIER 1
+#endif
+__device__ __forceinline__ void lds_barrier() {
+  if (PF_LDS_BARRIER) __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else __syncthreads();
+}
 constexpr int kCoarseMin = 4;
 // 3-D restriction through LDS-staged fine planes (0: one thread per coarse
 // node gathering its 27 fine neighbours)
@@ -562,7 +577,7 @@ __global__ void __launch_bounds__(RCX * RCY)
       const int q = tid + j * RCX * RCY;
       if (q < NQ) fsd[buf][q / FX][q % FX] = pf[j];
     }
-    __syncthreads();
+    lds_barrier();
     if (z + 1 <= zlast) fetch(z + 1);
     T2 p;
     p.x = 0;
@@ -896,7 +911,7 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
     const int cm = k & 1, cp = cm ^ 1;
     store_x(xa, sp);  // plane z + 1
     store_c(cp);      // cell plane z
-    __syncthreads();
+    lds_barrier();
     const T2 cur_b = nb;
     if (z + 1 < zend) {
       fetch_x(xa, z + 2);
@@ -1048,7 +1063,9 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
         }
       }
     }
-    __syncthreads();
+    // this plane's LDS reads done before the next plane is staged; its global
+    // stores are left in flight (no thread reads another's outputs here)
+    lds_barrier();
   }
 }
 
