@@ -433,14 +433,12 @@ __device__ __forceinline__ void quad2(const Geo& G, const double (&ng)[NG][4],
 // J = a^2 g + a |g|^2 da/dg (gradient of a^2 |g|^2 / 2).
 template <int DIM>
 struct Aniso {
-  // primal quantities kept for the tangent: q = |g|^2, S = sum g^4, iQ = 1/Q,
-  // iQ2 = 1/Q^2, a, a^2, b = 16 eps4/Q^2, aqc = a q b, SQ = S/Q, g2_k = g_k^2,
-  // gm_k = g_k^2 - S/Q and t_k with J_k = g_k t_k, t_k = a^2 + aqc gm_k
-  // (da/dg_k = b g_k gm_k).
-  double q, S, iQ, iQ2, a, a2, b, aqc, SQ, g2[3], gm[3], t[3], J[3];
-  // kFluxOnly: only J is used afterwards (the residual): t_k is formed as
-  // (a^2 - aqc S/Q) + aqc g_k^2, one FMA per component, and gm is not formed
-  template <bool kFluxOnly = false>
+  // primal quantities kept for the tangent and adjoint: q = |g|^2, S = sum g^4,
+  // iQ = 1/Q, iQ2 = 1/Q^2, a, a^2, b = 16 eps4/Q^2, aqc = a q b, SQ = S/Q,
+  // g2_k = g_k^2 (da/dg_k = b g_k (g_k^2 - S/Q)); J is the flux, with
+  // J_k = g_k t_k, t_k = a^2 + aqc (g_k^2 - S/Q) formed as
+  // (a^2 - aqc S/Q) + aqc g_k^2 (one FMA per component).
+  double q, S, iQ, iQ2, a, a2, b, aqc, SQ, g2[3], J[3];
   __device__ __forceinline__ void flux(const double* g, const Geo& G) {
     q = 0.0;
     S = 0.0;
@@ -457,25 +455,9 @@ struct Aniso {
     a2 = a * a;
     b = G.e16 * iQ2;
     aqc = (a * q) * b;
-    if constexpr (kFluxOnly) {
-      const double K0 = fma(-aqc, SQ, a2);
+    const double K0 = fma(-aqc, SQ, a2);
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        t[k] = fma(aqc, g2[k], K0);
-        J[k] = g[k] * t[k];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) {
-        gm[k] = g2[k] - SQ;
-        t[k] = fma(aqc, gm[k], a2);
-        J[k] = g[k] * t[k];
-      }
-    }
-  }
-  // da/dg_k = 16 eps4 g_k (g_k^2 - S/Q)/Q^2 (after flux())
-  __device__ __forceinline__ double dadg(const double* g, int k, const Geo&) const {
-    return b * (g[k] * gm[k]);
+    for (int k = 0; k < DIM; ++k) J[k] = g[k] * fma(aqc, g2[k], K0);
   }
   // Directional derivative along v (after flux()): out = (dJ/dg) v, the
   // Hessian of a^2 |g|^2 / 2 times v (symmetric), plus extra g_k (g_k^2 - S/Q)
@@ -490,8 +472,7 @@ struct Aniso {
   // regrouped by component as
   //   out_k = v_k c_k + g_k (D g_k^2 + K1),  c_k = (a^2 - aqc S/Q) + 3 aqc g_k^2,
   //   D = d(aqc) + extra,  K1 = d(a^2) - aqc d(S/Q) - D S/Q:
-  // c_k depends on the primal only, three operations per component, and gm,
-  // t are not needed.
+  // c_k depends on the primal only: three operations per component.
   // gvo = g.v and gmv = sum g_k gm_k v_k = g3v - (S/Q) gv are returned too.
   template <bool kExtra>
   __device__ __forceinline__ void hvp_c(const double* g, const double* v, double extra,
@@ -543,7 +524,7 @@ struct PhysResidual {
                                              double*) {
     const double phi = gv[0], u = vv[0], dphi_dt = vv[1];
     Aniso<DIM> A;
-    A.template flux<true>(gg[0], G);
+    A.flux(gg[0], G);
     a2 = A.a * A.a;
     const double om = fma(-phi, phi, 1.0);
     const double R = om * fma(-G.lam * om, u, phi);  // phi - phi^3 - lambda (1-phi^2)^2 u

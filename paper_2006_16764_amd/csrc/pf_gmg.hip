@@ -896,15 +896,16 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
   // FP32 residual and Chebyshev steps: the node's own right-hand side one
   // plane ahead in registers, so that the compute phase waits on one global
   // read fewer (measured: the last step, which also reads d and writes FP64,
-  // and the FP64 sweeps are slower with it)
+  // and the FP64 sweeps are slower with it; steps that both read and write d
+  // would lose a wave per SIMD to the two extra registers)
   constexpr bool kPreB = sizeof(T) == 4 && OP <= 1 && FL != (kReadD | kWriteD);
   T2 nb{};
-  auto fetch_bd = [&](int z) {
+  auto fetch_b = [&](int z) {
     if constexpr (kPreB) {
       if (inside) nb = b[ibase + plane_n * z];
     }
   };
-  fetch_bd(z0);
+  fetch_b(z0);
   for (int z = z0; z < zend; ++z) {
     const int k = z - z0;
     const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
@@ -916,7 +917,7 @@ __global__ void __launch_bounds__(SBX * SBY) k_stencil3(LvK g, StArgs<T> A) {
     if (z + 1 < zend) {
       fetch_x(xa, z + 2);
       fetch_c(z + 1);
-      fetch_bd(z + 1);
+      fetch_b(z + 1);
     }
     (void)cur_b;
     if (inside) {
