@@ -241,7 +241,9 @@ __global__ void __launch_bounds__(256)
 __global__ void k_fd_eps(const double* __restrict__ uu, const double* __restrict__ vv,
                          double* __restrict__ eps) {
   const double nu = sqrt(uu[0]), nv = sqrt(vv[0]);
-  eps[0] = (nv > 0.0) ? 1.4901161193847656e-08 * (1.0 + nu) / nv : 0.0;
+  const double e = (nv > 0.0) ? 1.4901161193847656e-08 * (1.0 + nu) / nv : 0.0;
+  eps[0] = e;
+  eps[1] = e == 0.0 ? 0.0 : 1.0 / e;  // read by the product kernels instead of dividing
 }
 
 __global__ void k_sub_scalars(double* acc, const double* x, int k) {

@@ -203,7 +203,9 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd<MODE>)
   const int kzmax = min(KZ, G.n[2] - z0);  // element layers in this chunk
   const int ei = tid % TX, ej = tid / TX;  // this lane's element column
   const bool has_elem = ei < lxmax && ej < lymax;
-  const double eps = (MODE == MODE_FD) ? *eps_dev : 0.0;
+  // FD product: eps_dev holds eps and 1/eps (0 when eps is 0)
+  const double eps = (MODE == MODE_FD) ? eps_dev[0] : 0.0;
+  const double ieps = (MODE == MODE_FD) ? eps_dev[1] : 0.0;
 
   // node ownership for the gathers: lane owns node tid and, for tid < PN - 256, node 256 + tid
   constexpr int kSecond = PN - kThreads;  // 33
@@ -338,8 +340,7 @@ __global__ void __launch_bounds__(kThreads, kWavesPerSimd<MODE>)
     const long long g = gnode(G, x0 + lx, y0 + ly, z0 + lz);
     if (MODE == MODE_FD) {
       const double2 f0 = sf[kDma ? lz % 3 : lz & 1][n];
-      const double ie = eps == 0.0 ? 0.0 : 1.0 / eps;
-      out0[g] = make_double2((acc[0] - f0.x) * ie, (acc[1] - f0.y) * ie);
+      out0[g] = make_double2((acc[0] - f0.x) * ieps, (acc[1] - f0.y) * ieps);
     } else {
       if (out0) out0[g] = make_double2(acc[0], acc[1]);
       if (NO == 4 && out1) out1[g] = make_double2(acc[2 % NO], acc[3 % NO]);
@@ -581,11 +582,7 @@ __global__ void __launch_bounds__(256)
   const int lymax = min(TY, G.n[1] - y0);
   const int kzmax = min(KZ, G.n[2] - z0);
   const bool lastx = tx == T.ntx - 1, lasty = ty == T.nty - 1, lastz = tz == T.ntz - 1;
-  const double ie = [&] {
-    if (MODE != MODE_FD) return 0.0;
-    const double eps = *eps_dev;
-    return eps == 0.0 ? 0.0 : 1.0 / eps;
-  }();
+  const double ie = MODE == MODE_FD ? eps_dev[1] : 0.0;  // 1/eps
   for (int i = (int)threadIdx.x; i < SN; i += 256) {
     int lx, ly, lz;
     if (i < PN) {

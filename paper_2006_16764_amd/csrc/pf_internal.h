@@ -94,7 +94,9 @@ struct FgConst {
 // parameter sums only (no (dF/dU)^T w).
 enum Mode { MODE_RES = 0, MODE_FD = 1, MODE_JVP = 2, MODE_VJP = 3, MODE_VJPU = 4, MODE_VJPP = 5 };
 
-// 3-D single-pass kernels (pf_fused3.hip).
+// 3-D single-pass kernels (pf_fused3.hip).  For the FD product, eps_dev[0]
+// is the step eps and eps_dev[1] its reciprocal (0 when eps is 0), both
+// written by blas_fd_eps / blas_fd_eps_cached.
 long long fused3_side_len(const Geo& G);
 int fused3_tiles(const Geo& G);
 int launch_fused3(pf_problem* pb, int mode, const double* U, const double* Uprev, const double* v,
