@@ -1144,6 +1144,82 @@ __global__ void __launch_bounds__(1024)
   for (int i = threadIdx.x; i < n; i += blockDim.x) x_res[i] = xs[kCoarseDegree & 1][i];
 }
 
+// The same solve for coarsest grids of at most kCoarseSmall nodes: one node
+// per thread, whose 27 (9) stencil weights and neighbour indices are formed
+// once instead of at every step.  Same operations on the same values in the
+// same order as k_coarse: same bits.
+constexpr int kCoarseSmall = 256;
+template <int DIM, class T>
+__global__ void __launch_bounds__(kCoarseSmall)
+    k_coarse_small(LvK g, const T* __restrict__ c, const typename V2<T>::type* __restrict__ b,
+                   typename V2<T>::type* __restrict__ x_res, const double* __restrict__ coef) {
+  using T2 = typename V2<T>::type;
+  constexpr int NW = DIM == 3 ? 27 : 9;
+  __shared__ T2 xs[2][kCoarseSmall];
+  __shared__ T cs[kCoarseSmall];
+  const int n = (int)g.nnodes;
+  const int i = threadIdx.x;
+  const bool own = i < n;
+  if (i < g.ncells) cs[i] = c[i];
+  __syncthreads();
+  T2 bb{};
+  T w0[NW], w1[NW], dg0 = 1, dg1 = 1;
+  int nb[NW];
+  if (own) {
+    bb = b[i];
+    int ix, iy, iz;
+    node_ijk<DIM>(g, i, ix, iy, iz);
+    diag_only<DIM, T>(g, cs, ix, iy, iz, dg0, dg1);
+    stencil<DIM, T>(g, cs, ix, iy, iz, w0, w1);
+#pragma unroll
+    for (int tz = 0; tz < (DIM == 3 ? 3 : 1); ++tz) {
+      const int jz = DIM == 3 ? min(max(iz + tz - 1, 0), g.nn[2] - 1) : 0;
+#pragma unroll
+      for (int ty = 0; ty < 3; ++ty) {
+        const int jy = min(max(iy + ty - 1, 0), g.nn[1] - 1);
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx) {
+          const int jx = min(max(ix + tx - 1, 0), g.nn[0] - 1);
+          nb[tx + 3 * ty + 9 * tz] = (int)nidx(g, jx, jy, jz);
+        }
+      }
+    }
+  }
+  T2 dv{}, xv{};  // this node's direction and iterate
+  for (int k = 0; k < kCoarseDegree; ++k) {
+    const int src = k & 1, dst = src ^ 1;
+    const T al0 = (T)coef[4 * k + 0], al1 = (T)coef[4 * k + 1];
+    const T be0 = (T)coef[4 * k + 2], be1 = (T)coef[4 * k + 3];
+    if (own) {
+      T dn0, dn1, x0 = 0, x1 = 0;
+      if (k == 0) {
+        dn0 = div_diag(be0 * bb.x, dg0);
+        dn1 = div_diag(be1 * bb.y, dg1);
+      } else {
+        T y0 = 0, y1 = 0;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+          const T2 xn = xs[src][nb[t]];
+          y0 += w0[t] * xn.x;
+          y1 += w1[t] * xn.y;
+        }
+        const int tc = DIM == 3 ? 13 : 4;
+        x0 = xv.x;
+        x1 = xv.y;
+        dn0 = al0 * dv.x + be0 * (bb.x - y0) / w0[tc];
+        dn1 = al1 * dv.y + be1 * (bb.y - y1) / w1[tc];
+      }
+      dv.x = dn0;
+      dv.y = dn1;
+      xv.x = x0 + dn0;
+      xv.y = x1 + dn1;
+      xs[dst][i] = xv;
+    }
+    __syncthreads();
+  }
+  if (own) x_res[i] = xv;
+}
+
 __global__ void k_jacobi(Geo G, const double* __restrict__ c, const double2* __restrict__ r,
                          double2* __restrict__ z, double ae0, double ae1) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
@@ -1454,7 +1530,12 @@ int vcycle(pf_problem* pb, Hier<T>& H, size_t l, const double* r64, double* z64,
                          reinterpret_cast<const double2*>(r64), L.b, L.k.nnodes);
       PF_HIP_CHECK(hipGetLastError());
     }
-    if (L.k.nnodes <= kCoarseLdsNodes) {
+    if (L.k.nnodes <= kCoarseSmall) {
+      hipLaunchKernelGGL((k_coarse_small<DIM, T>), dim3(1), dim3(kCoarseSmall), 0, s, L.k,
+                         (const T*)L.c, (const typename V2<T>::type*)L.b, L.xb,
+                         (const double*)H.coarse_dev);
+      PF_HIP_CHECK(hipGetLastError());
+    } else if (L.k.nnodes <= kCoarseLdsNodes) {
       hipLaunchKernelGGL((k_coarse<DIM, T>), dim3(1), dim3(1024), 0, s, L.k, (const T*)L.c,
                          (const typename V2<T>::type*)L.b, L.xb, (const double*)H.coarse_dev);
       PF_HIP_CHECK(hipGetLastError());
