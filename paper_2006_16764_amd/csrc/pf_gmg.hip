@@ -1364,7 +1364,10 @@ int hier_alloc(pf_problem* pb, Hier<T>& H) {
     }
     L.k.nnodes = (long long)L.k.nn[0] * L.k.nn[1] * L.k.nn[2];
     L.k.ncells = (long long)L.k.n[0] * L.k.n[1] * L.k.n[2];
-    L.kz = use_tiled(L.k, G.dim) ? tiled_kz(L.k, min_groups) : 0;
+    // coarser levels march further, for half the workgroups: their chunks are
+    // short, and the halo planes every chunk re-reads cost more there than
+    // the compute units left idle (the 129^3 level of 256^3: 2 -> 4 planes)
+    L.kz = use_tiled(L.k, G.dim) ? tiled_kz(L.k, H.lv.empty() ? min_groups : (min_groups + 1) / 2) : 0;
     const size_t nb = (size_t)L.k.nnodes * sizeof(typename V2<T>::type);
     // registered before allocating, so that hier_free releases a partial level
     H.lv.push_back(L);
