@@ -134,7 +134,7 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1097791232,
+    "bytes": 1097762208,
     "sources_sha256": "27d3e26cfacfd3978941121f497d83d1db854fc2b3ffda2eb582c4b97848a077",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
