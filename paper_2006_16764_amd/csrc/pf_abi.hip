@@ -237,8 +237,13 @@ struct Op {
 // uses the column with s = 0, rho = 1; when it passes (or the cycle ends) the
 // products of u are formed at once and the column completed before the exact
 // residual is taken.  Two sweeps over the basis per iteration instead of three.
-int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol,
-           const pf_solver_opts& o, int* its_out, hipStream_t s) {
+// The right-hand side is bsign b (bsign = 1 or -1); bnorm is |b| when the
+// caller has it (the same norm2 value), else negative.  x is written by the
+// first solution update (x = Z y, no zero fill read back) or zeroed on a return
+// before it.
+int fgmres_cycles(pf_problem* pb, const Op& op, const double* b, double bsign, double bnorm,
+                  double* x, bool* xset, double rtol, const pf_solver_opts& o, int* its_out,
+                  hipStream_t s) {
   const long long n = pb->n_dof;
   const int m = o.gmres_m;
   double* V = pb->V;
@@ -249,9 +254,8 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   double* hp = pb->host_pinned;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   std::vector<double> hcol(m + 1), sv(m + 1), col(m + 1);
-  PF_HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-  double beta;
-  PF_TRY(norm2(pb, b, &beta, s));
+  double beta = bnorm;
+  if (!(bnorm >= 0.0)) PF_TRY(norm2(pb, b, &beta, s));
   *its_out = 0;
   if (!std::isfinite(beta)) {
     set_error("non-finite right-hand side in FGMRES");
@@ -260,6 +264,7 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   if (beta == 0.0) return PF_OK;
   const double target = rtol * beta;
   const double* rhs = b;
+  double rsign = bsign;  // the sign of rhs in the right-hand side (1 after a restart)
   int total = 0;
   bool converged = false;
   double resid = beta;
@@ -298,7 +303,7 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
   };
   while (true) {
     // V_0 = r / |r|, final
-    PF_TRY(blas_axpby(1.0 / resid, rhs, 0.0, rhs, V, n, s));
+    PF_TRY(blas_axpby(rsign / resid, rhs, 0.0, rhs, V, n, s));
     std::fill(g.begin(), g.end(), 0.0);
     std::fill(H.begin(), H.end(), 0.0);
     g[0] = resid;
@@ -407,18 +412,20 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
     std::memcpy(pb->host_pinned + kSlotHostY, y.data(), jend * sizeof(double));
     PF_HIP_CHECK(hipMemcpyAsync(ydev, pb->host_pinned + kSlotHostY, jend * sizeof(double),
                                 hipMemcpyHostToDevice, s));
-    PF_TRY(blas_combine(pb, Z, n, jend, ydev, x, n, s));
+    PF_TRY(blas_combine(pb, Z, n, jend, ydev, x, n, s, !*xset));
+    *xset = true;
     PF_HIP_CHECK(hipStreamSynchronize(s));
     if (converged || total >= o.gmres_maxit) break;
     // restart: r = b - A x
     PF_TRY(op.apply(x, r, s));
-    PF_TRY(blas_axpby(1.0, b, -1.0, r, r, n, s));
+    PF_TRY(blas_axpby(bsign, b, -1.0, r, r, n, s));
     PF_TRY(norm2(pb, r, &resid, s));
     if (resid <= target) {
       converged = true;
       break;
     }
     rhs = r;
+    rsign = 1.0;
   }
   *its_out = total;
   if (!converged) {
@@ -426,6 +433,14 @@ int fgmres(pf_problem* pb, const Op& op, const double* b, double* x, double rtol
     return PF_ERR_LINEAR;
   }
   return PF_OK;
+}
+
+int fgmres(pf_problem* pb, const Op& op, const double* b, double bsign, double bnorm, double* x,
+           double rtol, const pf_solver_opts& o, int* its_out, hipStream_t s) {
+  bool xset = false;
+  const int rc = fgmres_cycles(pb, op, b, bsign, bnorm, x, &xset, rtol, o, its_out, s);
+  if (!xset) PF_HIP_CHECK(hipMemsetAsync(x, 0, pb->n_dof * sizeof(double), s));
+  return rc;
 }
 
 void stats_reset(pf_solver_stats* st) {
@@ -478,6 +493,9 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
   const long long n = pb->n_dof;
   double* F = pb->tmp_vec[0];
   double* dU = pb->tmp_vec[1];
+  // the accepted state alternates between U and tmp_vec[2], the trial state
+  // taking the other one: no copy per Newton step, one at the end if needed
+  double* Uc = U;
   double* Ut = pb->tmp_vec[2];
   // tmp_vec[3] is FGMRES's restart vector
   double* Ft = pb->tmp_vec[4];
@@ -488,6 +506,10 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
     if (!load) return norm2(pb, X, out, s);
     PF_TRY(blas_axpby(1.0, X, 1.0, load, B, n, s));
     return norm2(pb, B, out, s);
+  };
+  auto sync_u = [&]() -> int {
+    if (Uc != U) PF_HIP_CHECK(hipMemcpyAsync(U, Uc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return PF_OK;
   };
   PF_TRY(launch_residual_family(pb, MODE_RES, U, Uprev, nullptr, nullptr, nullptr, F, nullptr,
                                 nullptr, s, coef));
@@ -512,29 +534,32 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
         st->status = PF_ERR_NOT_CONVERGED;
         st->f_final = f;
       }
+      PF_TRY(sync_u());
       return PF_ERR_NOT_CONVERGED;
     }
     // the cell coefficients of the preconditioner came with the residual at U
     PF_TRY(pc_setup_prepared(pb, o.pc, o.pc_precision, s));
+    // right-hand side -(F + load), whose norm is f: -F itself without a load
     if (load) PF_TRY(blas_axpby(-1.0, F, -1.0, load, B, n, s));
-    else PF_TRY(blas_axpby(-1.0, F, 0.0, F, B, n, s));
-    Op op{pb, U, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
+    Op op{pb, Uc, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
     PF_TRY(op.prepare(s));
     int its = 0;
-    int rc = fgmres(pb, op, B, dU, eta, o, &its, s);
+    int rc = load ? fgmres(pb, op, B, 1.0, f, dU, eta, o, &its, s)
+                  : fgmres(pb, op, F, -1.0, f, dU, eta, o, &its, s);
     if (st) {
       st->gmres_its_total += its;
       if (l < PF_MAX_LOG) st->gmres_its[l] = its;
     }
     if (rc != PF_OK && rc != PF_ERR_LINEAR) {
       if (st) st->status = rc;
+      PF_TRY(sync_u());
       return rc;
     }
     // backtracking: Lambda = 1, 1/2, ... until |F(U + Lambda dU)| <= |F(U)|
     double lam = 1.0, ft = 0.0;
     bool ok = false;
     for (int bt = 0; bt <= o.max_backtracks; ++bt) {
-      PF_TRY(blas_axpby(1.0, U, lam, dU, Ut, n, s));
+      PF_TRY(blas_axpby(1.0, Uc, lam, dU, Ut, n, s));
       PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr,
                                     nullptr, s, coef));
       PF_TRY(norm_loaded(Ft, &ft));
@@ -551,10 +576,11 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
         st->status = std::isfinite(ft) ? PF_ERR_LINESEARCH : PF_ERR_NONFINITE;
         st->f_final = f;
       }
+      PF_TRY(sync_u());
       return std::isfinite(ft) ? PF_ERR_LINESEARCH : PF_ERR_NONFINITE;
     }
-    PF_HIP_CHECK(hipMemcpyAsync(U, Ut, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    std::swap(F, Ft);  // the accepted trial residual becomes F (both are work vectors)
+    std::swap(Uc, Ut);  // the accepted trial state
+    std::swap(F, Ft);   // and its residual (both are work vectors)
     // forcing term for the next linear solve
     const double ratio = ft / f;
     double en = o.gamma * std::pow(ratio, o.omega);
@@ -566,6 +592,7 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
     ++l;
     if (st && l <= PF_MAX_LOG) st->fnorm[l] = f;
   }
+  PF_TRY(sync_u());
   if (st) {
     st->newton_its = l;
     st->f_final = f;
@@ -983,7 +1010,7 @@ int pf_linear_solve(pf_problem* pb, const double* U, const double* Uprev, const 
   Op op{pb, U, Uprev, F, kind};
   PF_TRY(op.prepare(s));
   int its = 0;
-  int rc = fgmres(pb, op, b, x, rtol, *opts, &its, s);
+  int rc = fgmres(pb, op, b, 1.0, -1.0, x, rtol, *opts, &its, s);
   if (stats) {
     stats->gmres_its_total = its;
     stats->gmres_its[0] = its;
@@ -1104,7 +1131,7 @@ int pf_adjoint_step(pf_problem* pb, const double* U, const double* Uprev, const 
   PF_TRY(pc_setup(pb, U, opts->pc, opts->pc_precision, s));
   Op op{pb, U, Uprev, nullptr, 2};
   int its = 0;
-  int rc = fgmres(pb, op, mu, lam, opts->tau_r, *opts, &its, s);
+  int rc = fgmres(pb, op, mu, 1.0, -1.0, lam, opts->tau_r, *opts, &its, s);
   if (stats) {
     stats->gmres_its_total = its;
     stats->gmres_its[0] = its;
@@ -1143,7 +1170,7 @@ int pf_adjoint_solve(pf_problem* pb, const double* U, const double* Uprev, const
   PF_TRY(pc_setup(pb, U, opts->pc, opts->pc_precision, s));
   Op op{pb, U, Uprev, nullptr, 2};
   int its = 0;
-  const int rc = fgmres(pb, op, rhs, lam, opts->tau_r, *opts, &its, s);
+  const int rc = fgmres(pb, op, rhs, 1.0, -1.0, lam, opts->tau_r, *opts, &its, s);
   if (stats) {
     stats->gmres_its_total = its;
     stats->gmres_its[0] = its;

@@ -95,15 +95,17 @@ __global__ void __launch_bounds__(kRedThreads)
   }
 }
 
-// x[i] += sum_j coef[j] * V_j[i]  (runtime k, coefficients on the device)
+// x[i] += sum_j coef[j] * V_j[i]  (runtime k, coefficients on the device), or
+// x[i] = that sum (assign)
 __global__ void __launch_bounds__(256)
     k_combine(const double* __restrict__ V, long long ld, int k, const double* __restrict__ coef,
-              double* __restrict__ x, long long n) {
+              double* __restrict__ x, long long n, int assign) {
   const long long n2 = n / 2;
   double2* x2 = reinterpret_cast<double2*>(x);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
        i += (long long)gridDim.x * blockDim.x) {
-    double2 a = x2[i];
+    // assign: x = sum_j coef[j] V_j, the same sums as from an x of zeros
+    double2 a = assign ? make_double2(0.0, 0.0) : x2[i];
     for (int j = 0; j < k; ++j) {
       const double c = coef[j];
       const double2 v = reinterpret_cast<const double2*>(V + (long long)j * ld)[i];
@@ -309,11 +311,11 @@ int blas_dcgs_update(double* V, long long ld, int j, const double* dots_dev, dou
 }
 
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
-                 double* x, long long n, hipStream_t s) {
+                 double* x, long long n, hipStream_t s, bool assign) {
   (void)pb;
-  if (k <= 0) return PF_OK;
+  if (k <= 0 && !assign) return PF_OK;
   hipLaunchKernelGGL(k_combine, dim3(grid_for(n / 2, 256, 8192)), dim3(256), 0, s, V, ld, k,
-                     coef_dev, x, n);
+                     coef_dev, x, n, assign ? 1 : 0);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

@@ -183,8 +183,9 @@ int blas_dcgs_dots(pf_problem* pb, const double* V, long long ld, int j, long lo
                    double* out_dev, hipStream_t s, double* out_host = nullptr);
 int blas_dcgs_update(double* V, long long ld, int j, const double* dots_dev, double hj,
                      double inv_rho, double inv_eta, long long n, hipStream_t s);
+// x += sum_{j<k} coef_dev[j] V_j; assign: x = that sum (x not read; zeros when k = 0)
 int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const double* coef_dev,
-                 double* x, long long n, hipStream_t s);
+                 double* x, long long n, hipStream_t s, bool assign = false);
 int blas_scale_copy(const double* x, const double* alpha_dev, int invert, double* y,
                     long long n, hipStream_t s);
 int blas_axpby(double a, const double* x, double b, const double* y, double* z, long long n,
