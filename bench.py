@@ -134,8 +134,8 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1097762208,
-    "sources_sha256": "27d3e26cfacfd3978941121f497d83d1db854fc2b3ffda2eb582c4b97848a077",
+    "bytes": 1097845720,
+    "sources_sha256": "77bdd9dca72b0173ff8c433ffbb46bc8120d3f29bdaf69a640bd6df03969e4a5",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
                    "paper_2006_16764_amd/csrc/pf_internal.h")
