@@ -204,10 +204,11 @@ struct Op {
   const double* F0;  // F(U) for the FD product
   int kind;          // 0 = J (FD), 1 = J (analytic), 2 = J^T
   const double* unorm2 = nullptr;  // |U|^2 on the device (FD), computed by prepare()
-  int prepare(hipStream_t s) {
+  // have_unorm2: the slot already holds |U|^2 (formed with the trial state)
+  int prepare(hipStream_t s, bool have_unorm2 = false) {
     if (kind != 0) return PF_OK;
     double* d = pb->red_out + kSlotUnorm;
-    PF_TRY(blas_multidot(pb, U, pb->n_dof, 1, U, pb->n_dof, d, s));
+    if (!have_unorm2) PF_TRY(blas_multidot(pb, U, pb->n_dof, 1, U, pb->n_dof, d, s));
     unorm2 = d;
     return PF_OK;
   }
@@ -542,7 +543,7 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
     // right-hand side -(F + load), whose norm is f: -F itself without a load
     if (load) PF_TRY(blas_axpby(-1.0, F, -1.0, load, B, n, s));
     Op op{pb, Uc, Uprev, F, o.jv_mode == PF_JV_FD ? 0 : 1};
-    PF_TRY(op.prepare(s));
+    PF_TRY(op.prepare(s, l > 0));
     int its = 0;
     int rc = load ? fgmres(pb, op, B, 1.0, f, dU, eta, o, &its, s)
                   : fgmres(pb, op, F, -1.0, f, dU, eta, o, &its, s);
@@ -559,7 +560,8 @@ int newton_impl(pf_problem* pb, const double* Uprev, const double* load, double*
     double lam = 1.0, ft = 0.0;
     bool ok = false;
     for (int bt = 0; bt <= o.max_backtracks; ++bt) {
-      PF_TRY(blas_axpby(1.0, Uc, lam, dU, Ut, n, s));
+      // the trial state and its |.|^2, which the next step's FD products take
+      PF_TRY(blas_axpby_norm(pb, 1.0, Uc, lam, dU, Ut, n, pb->red_out + kSlotUnorm, s));
       PF_TRY(launch_residual_family(pb, MODE_RES, Ut, Uprev, nullptr, nullptr, nullptr, Ft, nullptr,
                                     nullptr, s, coef));
       PF_TRY(norm_loaded(Ft, &ft));

@@ -78,6 +78,31 @@ __global__ void __launch_bounds__(kRedThreads)
   }
 }
 
+// z = a x + b y as k_axpby, and the partials of |z|^2 in the squared-norm
+// order of k_multidot (same grid, same per-thread and block sums): with
+// k_reduce, the same |z|^2 as a multi-dot of z with itself.
+__global__ void __launch_bounds__(kRedThreads)
+    k_axpby_norm(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                 double* __restrict__ z, long long n, double* __restrict__ partials) {
+  __shared__ double sh[kRedThreads / 64];
+  const int nb = gridDim.x;
+  const long long n2 = n / 2;
+  const double2* x2 = reinterpret_cast<const double2*>(x);
+  const double2* y2 = reinterpret_cast<const double2*>(y);
+  double2* z2 = reinterpret_cast<double2*>(z);
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < n2;
+       i += (long long)nb * kRedThreads) {
+    const double2 u = x2[i], v = y2[i];
+    const double2 w = make_double2(fma(a, u.x, b * v.x), fma(a, u.y, b * v.y));
+    z2[i] = w;
+    acc = fma(w.x, w.x, acc);
+    acc = fma(w.y, w.y, acc);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 // out[j] = scale * sum_b partials[j * nparts + b], fixed order per thread then
 // fixed block butterfly; one block per j.  out_host (may be NULL): the same
 // values into mapped host memory, read by the host after the stream syncs.
@@ -272,6 +297,18 @@ int blas_multidot(pf_problem* pb, const double* V, long long ld, int k, const do
   PF_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, s, pb->red_partials, nb, out_dev, 1.0,
                      out_host);
+  PF_HIP_CHECK(hipGetLastError());
+  return PF_OK;
+}
+
+int blas_axpby_norm(pf_problem* pb, double a, const double* x, double b, const double* y, double* z,
+                    long long n, double* out_dev, hipStream_t s) {
+  const int nb = pb->n_red_blocks;
+  hipLaunchKernelGGL(k_axpby_norm, dim3(nb), dim3(kRedThreads), 0, s, a, x, b, y, z, n,
+                     pb->red_partials);
+  PF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, pb->red_partials, nb, out_dev, 1.0,
+                     nullptr);
   PF_HIP_CHECK(hipGetLastError());
   return PF_OK;
 }

@@ -188,6 +188,9 @@ int blas_combine(pf_problem* pb, const double* V, long long ld, int k, const dou
                  double* x, long long n, hipStream_t s, bool assign = false);
 int blas_scale_copy(const double* x, const double* alpha_dev, int invert, double* y,
                     long long n, hipStream_t s);
+// z = a x + b y, and |z|^2 into out_dev (device), the value blas_multidot of z with itself gives
+int blas_axpby_norm(pf_problem* pb, double a, const double* x, double b, const double* y, double* z,
+                    long long n, double* out_dev, hipStream_t s);
 int blas_axpby(double a, const double* x, double b, const double* y, double* z, long long n,
                hipStream_t s);
 int blas_fd_eps(pf_problem* pb, const double* U, const double* v, long long n, double* eps_dev,
