@@ -353,6 +353,11 @@ __global__ void __launch_bounds__(kT)
   c[e] = acc / wsum;
 }
 
+template <class T>
+__global__ void k_convert(const double* __restrict__ x, T* __restrict__ y, long long n) {
+  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
+  if (i < n) y[i] = (T)x[i];
+}
 
 // coarse cell = mean of its 2^dim children
 template <int DIM, class T>
@@ -384,36 +389,6 @@ __global__ void __launch_bounds__(kT) k_diag(LvK g, const T* __restrict__ c, T* 
   T d0, d1;
   diag_only<DIM, T>(g, c, ix, iy, iz, d0, d1);
   dg[i] = d0;
-}
-
-// Finest level from the FP64 cell coefficients in one pass by node: the FP32
-// coefficient of the cell whose lower corner the node is, and the node's
-// phi-block diagonal summed from the converted values in diag_only's order
-// (k_convert and k_diag in one sweep; same bits).
-template <int DIM, class T>
-__global__ void __launch_bounds__(kT)
-    k_convert_diag(LvK g, const double* __restrict__ c64, T* __restrict__ c, T* __restrict__ dg) {
-  int ix, iy, iz;
-  long long i;
-  if (!plane_node(g, ix, iy, iz, i)) return;
-  constexpr int NZ = DIM == 3 ? 2 : 1;
-  T sum = 0;
-#pragma unroll
-  for (int bz = 0; bz < NZ; ++bz)
-#pragma unroll
-    for (int by = 0; by < 2; ++by)
-#pragma unroll
-      for (int bx = 0; bx < 2; ++bx) {
-        const int cx = ix - 1 + bx, cy = iy - 1 + by, cz = DIM == 3 ? iz - 1 + bz : 0;
-        const bool e = cx >= 0 && cx < g.n[0] && cy >= 0 && cy < g.n[1] &&
-                       (DIM == 2 || (cz >= 0 && cz < g.n[2]));
-        if (e) sum += (T)c64[cx + (long long)g.n[0] * (cy + (long long)g.n[1] * cz)];
-      }
-  dg[i] = (T)g.Ae[0][0] * sum;
-  if (ix < g.n[0] && iy < g.n[1] && (DIM == 2 || iz < g.n[2])) {
-    const long long e = ix + (long long)g.n[0] * (iy + (long long)g.n[1] * iz);
-    c[e] = (T)c64[e];
-  }
 }
 
 // num / d for a Jacobi diagonal d: times the hardware reciprocal estimate
@@ -1467,13 +1442,12 @@ int hier_setup(pf_problem* pb, Hier<T>& H, const double* c0_dev, hipStream_t s) 
       symbol_extremes(DIM, L.h, sm[f], sk[f], &L.lmin[f], &L.lmax[f]);
     }
     if (l == 0) {
-      hipLaunchKernelGGL((k_convert_diag<DIM, T>), plane_grid(L.k), dim3(kT), 0, s, L.k, c0_dev,
-                         L.c, L.dg);
-      PF_HIP_CHECK(hipGetLastError());
-      continue;
+      hipLaunchKernelGGL((k_convert<T>), dim3(blocks(L.k.ncells)), dim3(kT), 0, s, c0_dev, L.c,
+                         L.k.ncells);
+    } else {
+      hipLaunchKernelGGL((k_coarsen<DIM, T>), dim3(blocks(L.k.ncells)), dim3(kT), 0, s,
+                         H.lv[l - 1].k, L.k, (const T*)H.lv[l - 1].c, L.c);
     }
-    hipLaunchKernelGGL((k_coarsen<DIM, T>), dim3(blocks(L.k.ncells)), dim3(kT), 0, s,
-                       H.lv[l - 1].k, L.k, (const T*)H.lv[l - 1].c, L.c);
     PF_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL((k_diag<DIM, T>), plane_grid(L.k), dim3(kT), 0, s, L.k, (const T*)L.c, L.dg);
     PF_HIP_CHECK(hipGetLastError());
