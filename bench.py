@@ -134,8 +134,8 @@ BYTES_PER_NODE_RES = 48  # U, U^n read, F written (16 B each)
 # carried over to new sources).
 RESIDUAL_TRAFFIC = {
     "workload": "seeds3d_256",
-    "bytes": 1097845720,
-    "sources_sha256": "77bdd9dca72b0173ff8c433ffbb46bc8120d3f29bdaf69a640bd6df03969e4a5",
+    "bytes": 1097776352,
+    "sources_sha256": "3e5bea3ed740c915c011467c5a98a91f3c3cf2e9f721f81426302cb58ebeafc0",
 }
 TRAFFIC_SOURCES = ("paper_2006_16764_amd/csrc/pf_fused3.hip", "paper_2006_16764_amd/csrc/pf_element.h",
                    "paper_2006_16764_amd/csrc/pf_internal.h")
